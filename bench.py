@@ -1,0 +1,204 @@
+"""Throughput of the autotuned leapfrog star-stencil step on one MI355X.
+
+Workload: 512^3 layered velocity model (20 layers, 1500-4500 m/s, 2% noise,
+seed 13108232), h = 10 m, Courant 0.4, 8th order (R = 4), FP32, centred 15 Hz
+Ricker source, the time loop's steps W..W+K-1 timed after W warm-up steps.
+A "step" is one leapfrog update of all 512^3 points (one sweep launch with the
+source fused). Before the timed region the blocksize search picks the tile
+(its cost is reported, not timed); the plain-tiling kernel and the built-in
+default tile are timed on the same buffers for comparison.
+
+Prints one JSON line (rank 0). The roofline entry uses 16 algorithmic bytes
+per point update (read u^n, u^{n-1}, kappa; write u^{n+1}) divided by the
+sweep's average duration from HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 16
+METRIC = "Gpoint-updates/s + % of HBM roofline, 512^3 8th-order FP32 vs plain tiling"
+
+
+def sweep_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sweep.hpp", "kernels_radius.hip"):
+        with open(os.path.join(ROOT, "paper_1310_8232_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(tile: dict, n_points: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source and the chosen tile."""
+    path = os.path.join(ROOT, "profiles", "sweep_512_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != sweep_source_hash():
+        return None
+    key = "{kind}-{bx}-{by}-{ry}-{dz}-{vw}-{xcd}-{pf}".format(**tile)
+    entry = rec.get("tiles", {}).get(key)
+    if not entry:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def time_steps(prop, a, b, nsteps, it0, src, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    a, b = prop.run(a, b, nsteps, src, it0=it0, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), a, b
+
+
+def cpu_baseline(cfg, budget_s: float):
+    import numpy as np
+
+    import oracle
+    kap = oracle.kappa(cfg["v"], cfg["dt"], cfg["h"])
+    z = np.zeros(kap.shape)
+    amp = cfg["amp"].astype(np.float64)
+    t0 = time.perf_counter()
+    uc, up = oracle.leapfrog(kap, z, z, cfg["radius"], 1, src_idx=cfg["src_idx"], amp=amp)
+    t1 = time.perf_counter() - t0
+    more = max(0, min(int(budget_s / max(t1, 1e-3)) - 1, cfg["nt"] - 1))
+    t0 = time.perf_counter()
+    if more:
+        oracle.leapfrog(kap, uc, up, cfg["radius"], more, it0=1, src_idx=cfg["src_idx"], amp=amp)
+    t2 = time.perf_counter() - t0
+    steps = 1 + more
+    npts = kap.size
+    return {"value": npts * steps / (t1 + t2) / 1e9, "unit": "Gpt/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {steps} leapfrog steps of the same {cfg['nx']}x{cfg['ny']}x{cfg['nz']} "
+                      f"layered workload from rest (source on), {t1 + t2:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512, help="grid points per axis")
+    ap.add_argument("--radius", type=int, default=4)
+    ap.add_argument("--tune-parts", type=int, default=0, help="0 = every tile, P >= 2 = P-part grid")
+    ap.add_argument("--tune-iter", type=int, default=10)
+    ap.add_argument("--tune-rep", type=int, default=3)
+    ap.add_argument("--tile", type=str, default="", help="fixed tile bx,by,ry,dz,vw,xcd,pf (skips the search)")
+    ap.add_argument("--compare-steps", type=int, default=200, help="steps timed for plain and default tiles")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1310_8232_amd as p
+    import workloads
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    nt = args.warmup + args.steps
+    t0 = time.perf_counter()
+    cfg = workloads.config_layered(n, n, n, nt=max(nt, 1), radius=args.radius)
+    print(f"bench: inputs {cfg['name']} dt={cfg['dt']:.6e} vmax={cfg['vmax']:.1f} "
+          f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    prop = p.Propagator(torch.from_numpy(cfg["v"]).to(dev), cfg["h"], cfg["dt"], args.radius, vmax=cfg["vmax"])
+    idx = torch.tensor(cfg["src_idx"], dtype=torch.int64, device=dev)
+    amp = torch.from_numpy(cfg["amp"].reshape(-1, 1)).to(dev)
+    src = p.make_src(idx, amp)
+    npts = n * n * n
+
+    tune = None
+    if args.tile:
+        f = [int(x) for x in args.tile.split(",")]
+        prop.tile = p.make_tile(p.TILE_ZMARCH, *f)
+    else:
+        sa = torch.zeros_like(prop.kappa)
+        sb = torch.zeros_like(prop.kappa)
+        rep, _, _ = prop.tune(sa, sb, n_iter=args.tune_iter, n_rep=args.tune_rep, parts=args.tune_parts)
+        del sa, sb
+        tune = {"policy": "MWMB", "n_candidates": rep["n_candidates"], "n_iter": args.tune_iter,
+                "n_rep": args.tune_rep, "min_time_ms": rep["min_time_ms"], "actual_time_ms": rep["actual_time_ms"],
+                "gap": rep["gap"], "seconds": rep["seconds"], "default_tile_ms": rep["default_time_ms"]}
+        print(f"bench: tuned {rep['tile']} nC={rep['n_candidates']} in {rep['seconds']:.1f}s "
+              f"gap={rep['gap']:+.4f}", file=sys.stderr, flush=True)
+    tile = prop.tile.as_dict()
+
+    a = torch.zeros_like(prop.kappa)
+    b = torch.zeros_like(prop.kappa)
+    compare = {}
+    if not args.no_compare:
+        chosen = prop.tile
+        for name, t in (("plain_tiling", p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1)),
+                        ("default_tile", p.StencilTile())):
+            prop.tile = t
+            k = min(args.compare_steps, args.steps)
+            ms, _, _ = time_steps(prop, a, b, k, 0, src, stream)
+            compare[name] = {"tile": prop.tile.as_dict(), "gpts": npts * k / (ms * 1e-3) / 1e9,
+                             "ms_per_step": ms / k}
+        prop.tile = chosen
+        a.zero_()
+        b.zero_()
+
+    # Warm-up, then exactly `steps` timed steps of the time loop.
+    a, b = prop.run(a, b, args.warmup, src, it0=0, stream=stream)
+    torch.cuda.synchronize()
+    ms, a, b = time_steps(prop, a, b, args.steps, args.warmup, src, stream)
+    if not bool(torch.isfinite(a).all()):
+        print("bench: non-finite wavefield", file=sys.stderr)
+        return 1
+    step_ms = ms / args.steps
+    gpts = npts / (step_ms * 1e-3) / 1e9
+    achieved = BYTES_PER_UPDATE * npts / (step_ms * 1e-3) / 1e9
+    traffic = load_traffic(tile, npts)
+    out = {
+        "metric": METRIC, "value": round(gpts, 3), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(step_ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{cfg['name']} layered model, 8th order (R={args.radius}) 25-point star, "
+                               f"FP32, Ricker source, {args.steps} timed steps",
+                   "grid": [n, n, n], "radius": args.radius, "tile": tile, "tune": tune,
+                   "plain_tiling": compare.get("plain_tiling"), "default_tile": compare.get("default_tile"),
+                   "speedup_vs_plain": (round(gpts / compare["plain_tiling"]["gpts"], 3)
+                                        if "plain_tiling" in compare else None)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        del a, b
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,213 @@
+/*
+ * C ABI of the MI355X (gfx950) blocked star-stencil library
+ * (libpaper_1310_8232_amd.so).
+ *
+ * The operation (paper: Section 2, the "3D model" step inside the time loop
+ * of Algorithm 1; 10th order in space, 2nd order in time; star stencil with
+ * neighbours along both directions of all three axes, Fig. 1(a)):
+ *
+ *   L u(p)   = sum_{d in x,y,z} [ c_0 u(p) + sum_{m=1..R} c_m (u(p + m e_d) + u(p - m e_d)) ]
+ *   u^{n+1}  = 2 u^n - u^{n-1} + kappa * L u^n,     kappa = (v dt / h)^2
+ *   u^{n+1}(s_j) += kappa(s_j) * amp[n][j]           (point sources)
+ *
+ * u is 0 outside the grid (zero Dirichlet ghost layer); every grid point is
+ * updated. c_m are the order-2R central second-difference weights. The
+ * paper's loop blocking (Section 3, Fig. 1(b)) becomes the workgroup tile;
+ * its blocksize search (Sections 3.2-3.3, 3.6, 3.7) becomes stencil_tune.
+ *
+ * Data layout: every field is a contiguous FP32 array [nz][ny][nx] in device
+ * memory, x unit-stride, point (z, y, x) at linear index (z*ny + y)*nx + x.
+ *
+ * Ownership: field pointers are borrowed device memory (e.g. torch tensors);
+ * the library never allocates, frees or retains them. A context owns only
+ * host state (sizes, coefficients, the chosen tile). Contexts are not
+ * thread-safe; separate contexts are independent.
+ *
+ * Errors: every call returns a stencil_status (0 = success, negative =
+ * failure). Arguments are validated before any launch; a failed call leaves
+ * the fields untouched and records a message readable with
+ * stencil_last_error. No C++ exception crosses this interface.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream). stencil_kappa and stencil_step only enqueue work: no allocation,
+ * no synchronisation, no host read of device memory, so they may be captured
+ * in a HIP graph.
+ */
+#ifndef PAPER_1310_8232_AMD_STENCIL_H
+#define PAPER_1310_8232_AMD_STENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STENCIL_OK = 0,
+    STENCIL_EINVAL = -1,        /* bad argument: size, radius, pointer, alignment, step index */
+    STENCIL_EUNSTABLE = -2,     /* vmax*dt/h above the leapfrog stability limit */
+    STENCIL_ENOMEM = -3,        /* host allocation failed */
+    STENCIL_EDEVICE = -4,       /* a HIP call failed (message in stencil_last_error) */
+    STENCIL_EUNSUPPORTED = -5,  /* storage type or tile this build does not provide */
+    STENCIL_EALIAS = -6         /* u_cur and u_prev_next overlap */
+} stencil_status;
+
+typedef struct stencil_ctx stencil_ctx;  /* opaque */
+
+typedef enum { STENCIL_F32 = 0 } stencil_storage;
+
+typedef enum {
+    STENCIL_TILE_AUTO = 0,   /* the context's current tile (tuned, cached or built-in default) */
+    STENCIL_TILE_PLAIN = 1,  /* plain tiling: one thread per point, workgroup bx*by*dz, taps read from memory */
+    STENCIL_TILE_ZMARCH = 2  /* xy tile staged in LDS, register queue marching dz planes along z */
+} stencil_tile_kind;
+
+/* The GPU form of the paper's blocksize (bi, bj, bk). For ZMARCH a workgroup
+ * of bx*by threads owns a (bx*vw) x (by*ry) tile in (x, y) and marches dz
+ * planes in z; each thread computes vw consecutive x points of ry
+ * consecutive rows. For PLAIN a workgroup is bx x by x dz threads. */
+typedef struct {
+    int32_t kind;   /* stencil_tile_kind */
+    int32_t bx;     /* threads along x */
+    int32_t by;     /* threads along y */
+    int32_t ry;     /* rows per thread along y (ZMARCH) */
+    int32_t dz;     /* planes per workgroup along z (ZMARCH); threads along z (PLAIN) */
+    int32_t vw;     /* x points per thread: 4 (needs nx % 4 == 0) or 1; 0 = pick */
+    int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
+    int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH) */
+} stencil_tile;
+
+typedef struct {
+    int64_t nx, ny, nz;   /* grid points, each >= 1 */
+    int32_t radius;       /* R in {3, 4, 5}: order 2R in space (4 = 8th order, 25 points; 5 = the paper's 10th) */
+    int32_t storage;      /* stencil_storage: STENCIL_F32 */
+    double h;             /* grid spacing (isotropic), > 0 */
+    double dt;            /* time step, > 0 */
+    double vmax;          /* largest velocity of the model, > 0, used for the stability check */
+    int32_t device;       /* HIP device ordinal of the fields */
+    stencil_tile tile;    /* kind 0 = tune cache entry if any, else the built-in default */
+} stencil_desc;
+
+/* Point sources (all device memory, borrowed): idx[n] linear indices,
+ * amp[nt][n] samples; step `it` adds kappa(idx[j]) * amp[it*n + j] to
+ * u^{it+1}(idx[j]) for j = 0..n-1 in order. Indices outside the grid are
+ * skipped by the kernels. */
+typedef struct {
+    int32_t n;
+    const int64_t *idx;
+    const float *amp;
+    int64_t nt;
+} stencil_src;
+
+typedef enum {
+    STENCIL_POLICY_WORST = 0,  /* MWMB (Eq. 2): worst of the per-replicate minima; the default */
+    STENCIL_POLICY_MIN = 1,    /* MMMB (Eq. 1) */
+    STENCIL_POLICY_AVG = 2,    /* MAMB (Eq. 3) */
+    STENCIL_POLICY_OB = 3      /* Original Block: fastest single measurement */
+} stencil_policy;
+
+typedef struct {
+    int32_t policy;          /* stencil_policy */
+    int32_t n_iter;          /* nI: timed steps per candidate (Section 3.2); 0 = 10 */
+    int32_t n_rep;           /* replicate passes over the same candidate list in the same order; 0 = 3 */
+    int32_t warmup;          /* untimed steps before each timing; 0 = 2, -1 = none */
+    int32_t parts;           /* 0 = every legal tile x the dz list; P >= 2 = Section 3.7's P-part grid */
+    int32_t include_plain;   /* 1 = also time plain-tiling candidates */
+    const char *cache_path;  /* tune cache file (read before, written after); NULL = none */
+    double *table;           /* optional out: [n_rep][table_cap] times in ms (row-major) */
+    stencil_tile *candidates;/* optional out: [table_cap] candidate tiles in timing order */
+    int32_t table_cap;
+} stencil_tune_opts;
+
+typedef struct {
+    stencil_tile tile;       /* chosen tile (also made the context's current tile) */
+    double min_time_ms;      /* MinTime: selection-phase time of n_iter steps */
+    double actual_time_ms;   /* ActualTime: verification-phase time of n_iter steps */
+    double gap;              /* (ActualTime - MinTime) / MinTime (Section 3.6) */
+    double default_time_ms;  /* n_iter steps with the built-in default tile, same conditions */
+    double seconds;          /* wall time of the whole search */
+    int32_t n_candidates;    /* nC */
+    int32_t from_cache;      /* 1 = taken from cache_path without timing */
+} stencil_tune_report;
+
+/* Create a context. Validates sizes, radius, storage, h, dt, vmax (> 0) and
+ * the stability limit vmax*dt/h <= stencil_cfl_limit(radius) (EUNSTABLE).
+ * Host-only: no HIP call. *out is set only on success. */
+stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out);
+
+/* Release a context (NULL is ignored). */
+void stencil_destroy(stencil_ctx *ctx);
+
+/* kappa(p) = (v(p) dt / h)^2 for every point, formed in FP64 and rounded
+ * once to FP32 (the model set-up of Section 2's scheme). v and kappa are
+ * device arrays of the grid's shape; they may be the same array. */
+stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void *stream);
+
+/* One leapfrog step n = it: reads u_cur = u^{it} and u_prev_next = u^{it-1},
+ * overwrites u_prev_next with u^{it+1}, then injects the sources (src may
+ * be NULL). Requires it < src->nt when src is given (EINVAL). u_cur and
+ * u_prev_next must not overlap (EALIAS); kappa must not overlap
+ * u_prev_next. Pointers must be 16-byte aligned when the tile uses vw = 4. */
+stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur,
+                            void *u_prev_next, int64_t it, const stencil_src *src, void *stream);
+
+/* The paper's two-phase blocksize search (Sections 3.2-3.3) on the
+ * production shape: the selection phase times every candidate for n_iter
+ * steps, n_rep times in the same fixed order, and reduces the table with
+ * opts->policy; the verification phase re-times the winner (ActualTime).
+ * scratch_a/scratch_b are device fields of the grid's shape used as u^n and
+ * u^{n-1}: their contents are overwritten. Synchronises `stream`. Sets the
+ * context's tile and fills *report. opts may be NULL (defaults). */
+stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a, void *scratch_b,
+                            const stencil_tune_opts *opts, stencil_tune_report *report, void *stream);
+
+/* Current tile of the context (after init, tune or set). */
+stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out);
+
+/* Replace the current tile; rejects tiles this build cannot run on the
+ * context's grid (EUNSUPPORTED) without changing the current one. */
+stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
+
+/* Legal ZMARCH tiles for a radius, with vw = 4 (vec4 != 0) or 1, dz = 0.
+ * Writes at most cap entries to out (out may be NULL) and returns the total
+ * count, or a negative stencil_status. */
+int32_t stencil_list_tiles(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap);
+
+/* FP32 weights the kernels use: out[0] = 3*c_0, out[m] = c_m (m = 1..R).
+ * Returns R+1, or EINVAL for an unsupported radius. */
+int32_t stencil_coefficients(int32_t radius, float *out);
+
+/* Largest stable v*dt/h for the radius (2 / sqrt(3 |c_0 + 2 sum_m (-1)^m c_m|)),
+ * or a negative value for an unsupported radius. */
+double stencil_cfl_limit(int32_t radius);
+
+/* Section 3.3's three-stage reduction of a timing table, host only.
+ * t[(i*n_cores + k)*n_cand + j] = time of candidate j of node i on core k;
+ * node i's candidate j has global id i*n_cand + j. Stage 1: per-core
+ * argmin; stage 2: per-node min / worst / closest-to-mean of the core
+ * winners (policy); stage 3: argmin over nodes. STENCIL_POLICY_OB takes the
+ * single smallest entry. Ties go to the lowest node, core, candidate.
+ * Writes the chosen id and its time. */
+stencil_status stencil_select(const double *t, int32_t n_nodes, int32_t n_cores, int32_t n_cand,
+                              int32_t policy, int32_t *best_id, double *best_time);
+
+/* Section 3.7's candidate list for one dimension of size S cut in P parts:
+ * 1 + floor(j*S/(P-1)), j = 0..P-1, last clamped to S, repeats dropped.
+ * Writes at most cap values and returns the count (or EINVAL). */
+int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap);
+
+/* Streaming copy of nbytes (multiple of 16, 16-byte aligned pointers) from
+ * src to dst on `stream`: a bandwidth reference for the sweep. */
+stencil_status stencil_copy_probe(const void *src, void *dst, int64_t nbytes, void *stream);
+
+/* Message for a status code (static storage). */
+const char *stencil_strerror(stencil_status s);
+
+/* Last error message recorded on the context ("" if none). */
+const char *stencil_last_error(const stencil_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_1310_8232_AMD_STENCIL_H */

@@ -1,0 +1,326 @@
+"""Python binding of libpaper_1310_8232_amd.so (C ABI in include/stencil.h).
+
+Argument marshalling only: every step of the computation runs in the gfx950
+kernels of the library. PyTorch provides device memory and streams. Importing
+this module fails loudly if the compiled library is missing; there is no CPU
+fallback.
+
+Functions carry the C names (``stencil_init``, ``stencil_step``, ...); they
+accept torch tensors or raw integer device pointers and raise
+``StencilError`` on a non-zero status. ``Propagator`` wraps a context for a
+leapfrog time loop.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpaper_1310_8232_amd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_1310_8232_amd/build.py` (hipcc, gfx950). There is no CPU fallback.")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- status codes and enums (include/stencil.h) ----------------------------
+OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EUNSUPPORTED, EALIAS = 0, -1, -2, -3, -4, -5, -6
+F32 = 0
+TILE_AUTO, TILE_PLAIN, TILE_ZMARCH = 0, 1, 2
+POLICY_WORST, POLICY_MIN, POLICY_AVG, POLICY_OB = 0, 1, 2, 3
+POLICIES = {"worst": POLICY_WORST, "mwmb": POLICY_WORST, "min": POLICY_MIN, "mmmb": POLICY_MIN,
+            "avg": POLICY_AVG, "mamb": POLICY_AVG, "ob": POLICY_OB}
+
+
+class StencilTile(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("bx", ctypes.c_int32), ("by", ctypes.c_int32),
+                ("ry", ctypes.c_int32), ("dz", ctypes.c_int32), ("vw", ctypes.c_int32),
+                ("xcd", ctypes.c_int32), ("pf", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+    def __repr__(self):
+        return "StencilTile(" + ", ".join(f"{k}={v}" for k, v in self.as_dict().items()) + ")"
+
+
+class StencilDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("radius", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("h", ctypes.c_double), ("dt", ctypes.c_double), ("vmax", ctypes.c_double),
+                ("device", ctypes.c_int32), ("tile", StencilTile)]
+
+
+class StencilSrc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("idx", ctypes.c_void_p), ("amp", ctypes.c_void_p),
+                ("nt", ctypes.c_int64)]
+
+
+class StencilTuneOpts(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("n_rep", ctypes.c_int32),
+                ("warmup", ctypes.c_int32), ("parts", ctypes.c_int32), ("include_plain", ctypes.c_int32),
+                ("cache_path", ctypes.c_char_p), ("table", ctypes.POINTER(ctypes.c_double)),
+                ("candidates", ctypes.POINTER(StencilTile)), ("table_cap", ctypes.c_int32)]
+
+
+class StencilTuneReport(ctypes.Structure):
+    _fields_ = [("tile", StencilTile), ("min_time_ms", ctypes.c_double), ("actual_time_ms", ctypes.c_double),
+                ("gap", ctypes.c_double), ("default_time_ms", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("n_candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sig = {
+    "stencil_init": (_i32, [ctypes.POINTER(StencilDesc), ctypes.POINTER(_vp)]),
+    "stencil_destroy": (None, [_vp]),
+    "stencil_kappa": (_i32, [_vp, _vp, _vp, _vp]),
+    "stencil_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
+    "stencil_tune": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(StencilTuneOpts),
+                            ctypes.POINTER(StencilTuneReport), _vp]),
+    "stencil_get_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
+    "stencil_set_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
+    "stencil_list_tiles": (_i32, [_i32, _i32, ctypes.POINTER(StencilTile), _i32]),
+    "stencil_coefficients": (_i32, [_i32, ctypes.POINTER(ctypes.c_float)]),
+    "stencil_cfl_limit": (ctypes.c_double, [_i32]),
+    "stencil_select": (_i32, [ctypes.POINTER(ctypes.c_double), _i32, _i32, _i32, _i32,
+                              ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
+    "stencil_pgrid": (_i32, [_i64, _i32, ctypes.POINTER(_i64), _i32]),
+    "stencil_copy_probe": (_i32, [_vp, _vp, _i64, _vp]),
+    "stencil_strerror": (ctypes.c_char_p, [_i32]),
+    "stencil_last_error": (ctypes.c_char_p, [_vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class StencilError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = stencil_strerror(status)
+        if ctx:
+            extra = _lib.stencil_last_error(ctx)
+            if extra:
+                msg = f"{msg}: {extra.decode()}"
+        raise StencilError(status, msg)
+
+
+def _ptr(x) -> int:
+    """Device pointer of a tensor (or an int passed through)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def stencil_strerror(status: int) -> str:
+    return _lib.stencil_strerror(status).decode()
+
+
+def stencil_last_error(ctx) -> str:
+    return _lib.stencil_last_error(ctx).decode()
+
+
+def make_tile(kind=TILE_ZMARCH, bx=0, by=0, ry=1, dz=0, vw=0, xcd=1, pf=0) -> StencilTile:
+    return StencilTile(kind, bx, by, ry, dz, vw, xcd, pf)
+
+
+def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile | None = None):
+    """Create a context; returns an opaque handle (int)."""
+    d = StencilDesc(nx, ny, nz, radius, F32, h, dt, vmax, device, tile if tile is not None else StencilTile())
+    out = _vp()
+    _check(_lib.stencil_init(ctypes.byref(d), ctypes.byref(out)))
+    return out.value
+
+
+def stencil_destroy(ctx):
+    _lib.stencil_destroy(ctx)
+
+
+def stencil_kappa(ctx, v, kappa, stream=None):
+    _check(_lib.stencil_kappa(ctx, _ptr(v), _ptr(kappa), _stream(stream)), ctx)
+
+
+def make_src(idx, amp) -> StencilSrc:
+    """Source description from device tensors idx [n] (int64) and amp [nt, n] (float32)."""
+    n = int(idx.numel())
+    nt = int(amp.shape[0])
+    return StencilSrc(n, _ptr(idx), _ptr(amp), nt)
+
+
+def stencil_step(ctx, kappa, u_cur, u_prev_next, it=0, src: StencilSrc | None = None, stream=None):
+    _check(_lib.stencil_step(ctx, _ptr(kappa), _ptr(u_cur), _ptr(u_prev_next), int(it),
+                             ctypes.byref(src) if src is not None else None, _stream(stream)), ctx)
+
+
+def stencil_tune(ctx, kappa, scratch_a, scratch_b, policy="worst", n_iter=0, n_rep=0, warmup=0, parts=0,
+                 include_plain=False, cache_path=None, table_cap=0, stream=None):
+    """Run the blocksize search. Returns (report dict, table [n_rep][nC] or None,
+    candidates list or None)."""
+    pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    table = (ctypes.c_double * (max(n_rep or 3, 1) * table_cap))() if table_cap else None
+    cands = (StencilTile * table_cap)() if table_cap else None
+    opts = StencilTuneOpts(pol, n_iter, n_rep, warmup, parts, int(bool(include_plain)),
+                           cache_path.encode() if cache_path else None,
+                           ctypes.cast(table, ctypes.POINTER(ctypes.c_double)) if table else None,
+                           ctypes.cast(cands, ctypes.POINTER(StencilTile)) if cands else None, table_cap)
+    rep = StencilTuneReport()
+    _check(_lib.stencil_tune(ctx, _ptr(kappa), _ptr(scratch_a), _ptr(scratch_b), ctypes.byref(opts),
+                             ctypes.byref(rep), _stream(stream)), ctx)
+    report = {"tile": rep.tile.as_dict(), "min_time_ms": rep.min_time_ms, "actual_time_ms": rep.actual_time_ms,
+              "gap": rep.gap, "default_time_ms": rep.default_time_ms, "seconds": rep.seconds,
+              "n_candidates": rep.n_candidates, "from_cache": bool(rep.from_cache)}
+    tab = None
+    cl = None
+    if table_cap and not rep.from_cache:
+        nrep = n_rep or 3
+        nc = min(rep.n_candidates, table_cap)
+        tab = [[table[r * table_cap + c] for c in range(nc)] for r in range(nrep)]
+        cl = [cands[c].as_dict() for c in range(nc)]
+    return report, tab, cl
+
+
+def stencil_get_tile(ctx) -> StencilTile:
+    t = StencilTile()
+    _check(_lib.stencil_get_tile(ctx, ctypes.byref(t)), ctx)
+    return t
+
+
+def stencil_set_tile(ctx, tile: StencilTile):
+    _check(_lib.stencil_set_tile(ctx, ctypes.byref(tile)), ctx)
+
+
+def stencil_list_tiles(radius: int, vec4: bool = True):
+    n = _lib.stencil_list_tiles(radius, int(vec4), None, 0)
+    _check(min(n, 0))
+    arr = (StencilTile * max(n, 1))()
+    _lib.stencil_list_tiles(radius, int(vec4), arr, n)
+    return [arr[i] for i in range(n)]
+
+
+def stencil_coefficients(radius: int):
+    out = (ctypes.c_float * 8)()
+    n = _lib.stencil_coefficients(radius, out)
+    _check(min(n, 0))
+    return [out[i] for i in range(n)]
+
+
+def stencil_cfl_limit(radius: int) -> float:
+    r = _lib.stencil_cfl_limit(radius)
+    if r < 0:
+        raise StencilError(EINVAL, "unsupported radius")
+    return r
+
+
+def stencil_select(table, policy="worst"):
+    """table: nested [nodes][cores][candidates] times. Returns (global id, time)."""
+    nn = len(table)
+    nk = len(table[0])
+    nc = len(table[0][0])
+    flat = (ctypes.c_double * (nn * nk * nc))(*[v for node in table for row in node for v in row])
+    best = _i32()
+    t = ctypes.c_double()
+    pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    _check(_lib.stencil_select(flat, nn, nk, nc, pol, ctypes.byref(best), ctypes.byref(t)))
+    return best.value, t.value
+
+
+def stencil_pgrid(S: int, P: int):
+    n = _lib.stencil_pgrid(S, P, None, 0)
+    _check(min(n, 0))
+    out = (_i64 * max(n, 1))()
+    _lib.stencil_pgrid(S, P, out, n)
+    return [out[i] for i in range(n)]
+
+
+def stencil_copy_probe(src, dst, nbytes: int, stream=None):
+    _check(_lib.stencil_copy_probe(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
+
+
+class Propagator:
+    """A context bound to one grid and velocity model on one device.
+
+    ``v`` is a float32 CUDA tensor [nz, ny, nx]; kappa = (v dt / h)^2 is formed
+    on the device by the library. The time loop alternates the two wavefield
+    buffers: step n reads (u^n, u^{n-1}) and overwrites the u^{n-1} buffer
+    with u^{n+1}."""
+
+    def __init__(self, v, h: float, dt: float, radius: int = 4, vmax: float | None = None,
+                 tile: StencilTile | None = None):
+        import torch
+        if v.dtype != torch.float32 or not v.is_cuda or v.dim() != 3 or not v.is_contiguous():
+            raise ValueError("v must be a contiguous float32 CUDA tensor [nz, ny, nx]")
+        self.shape = tuple(v.shape)
+        nz, ny, nx = self.shape
+        if vmax is None:
+            vmax = float(v.max().item())
+        self.h, self.dt, self.radius = float(h), float(dt), int(radius)
+        self.device = v.device
+        self.ctx = stencil_init(nx, ny, nz, h, dt, vmax, radius, v.device.index or 0, tile)
+        self.kappa = torch.empty_like(v)
+        stencil_kappa(self.ctx, v, self.kappa)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            stencil_destroy(ctx)
+            self.ctx = None
+
+    def _check_field(self, t):
+        import torch
+        if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"fields must be contiguous float32 CUDA tensors of shape {self.shape}")
+
+    @property
+    def tile(self) -> StencilTile:
+        return stencil_get_tile(self.ctx)
+
+    @tile.setter
+    def tile(self, t: StencilTile):
+        stencil_set_tile(self.ctx, t)
+
+    def step(self, u_cur, u_prev_next, it: int = 0, src: StencilSrc | None = None, stream=None):
+        self._check_field(u_cur)
+        self._check_field(u_prev_next)
+        stencil_step(self.ctx, self.kappa, u_cur, u_prev_next, it, src, stream)
+
+    def run(self, u_cur, u_prev, nt: int, src: StencilSrc | None = None, it0: int = 0, stream=None):
+        """Advance nt steps from (u^{it0}, u^{it0-1}); returns the tensors now
+        holding (u^{it0+nt}, u^{it0+nt-1})."""
+        self._check_field(u_cur)
+        self._check_field(u_prev)
+        a, b = u_cur, u_prev
+        for it in range(it0, it0 + nt):
+            stencil_step(self.ctx, self.kappa, a, b, it, src, stream)
+            a, b = b, a
+        return a, b
+
+    def tune(self, scratch_a=None, scratch_b=None, **opts):
+        import torch
+        if scratch_a is None:
+            scratch_a = torch.zeros_like(self.kappa)
+        if scratch_b is None:
+            scratch_b = torch.zeros_like(self.kappa)
+        return stencil_tune(self.ctx, self.kappa, scratch_a, scratch_b, **opts)

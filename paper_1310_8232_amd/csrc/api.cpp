@@ -1,0 +1,765 @@
+// C-ABI runtime: context, validation, dispatch, the blocksize search and its
+// cache. Declarations and contracts: include/stencil.h.
+#include "../../include/stencil.h"
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using p1310::SweepArgs;
+using p1310::ZVariant;
+
+struct stencil_ctx {
+    stencil_desc d;
+    int R = 4;
+    float cf[p1310::kMaxRadius + 1] = {};  // 3*c_0, c_1..c_R in FP32
+    stencil_tile tile = {};
+    std::string err;
+};
+
+namespace {
+
+constexpr int kXcds = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
+constexpr int64_t kWindowLimit = (int64_t)1 << 31;
+
+// ---------------------------------------------------------------------------
+// Exact rational weights of the order-2R central second difference.
+// c_m = 2 (-1)^{m+1} (R!)^2 / (m^2 (R-m)! (R+m)!), c_0 = -2 sum c_m.
+// ---------------------------------------------------------------------------
+struct Rat {
+    long long n, d;
+};
+
+long long gcdll(long long a, long long b)
+{
+    if (a < 0) a = -a;
+    if (b < 0) b = -b;
+    while (b) {
+        long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a ? a : 1;
+}
+
+Rat rnorm(Rat r)
+{
+    if (r.d < 0) {
+        r.n = -r.n;
+        r.d = -r.d;
+    }
+    long long g = gcdll(r.n, r.d);
+    return {r.n / g, r.d / g};
+}
+
+Rat radd(Rat a, Rat b)
+{
+    long long g = gcdll(a.d, b.d);
+    return rnorm({a.n * (b.d / g) + b.n * (a.d / g), a.d / g * b.d});
+}
+
+Rat rmul(Rat a, long long k) { return rnorm({a.n * k, a.d}); }
+
+long long factll(int k)
+{
+    long long f = 1;
+    for (int i = 2; i <= k; ++i) f *= i;
+    return f;
+}
+
+bool radius_ok(int R) { return R >= 3 && R <= p1310::kMaxRadius; }
+
+void weights(int R, Rat *c)
+{
+    const long long rf = factll(R);
+    Rat sum = {0, 1};
+    for (int m = 1; m <= R; ++m) {
+        c[m] = rnorm({(m % 2 ? 2 : -2) * rf * rf, (long long)m * m * factll(R - m) * factll(R + m)});
+        sum = radd(sum, c[m]);
+    }
+    c[0] = rmul(sum, -2);
+}
+
+double rat_to_double(Rat r) { return (double)r.n / (double)r.d; }
+
+double cfl_limit_of(int R)
+{
+    Rat c[p1310::kMaxRadius + 1];
+    weights(R, c);
+    Rat s = c[0];
+    for (int m = 1; m <= R; ++m) s = radd(s, rmul(c[m], (m % 2) ? -2 : 2));
+    return 2.0 / std::sqrt(3.0 * std::fabs(rat_to_double(s)));
+}
+
+stencil_status fail(stencil_ctx *ctx, stencil_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+int64_t npoints(const stencil_ctx *c) { return c->d.nx * c->d.ny * c->d.nz; }
+
+bool vec4_ok(const stencil_ctx *c) { return c->d.nx % 4 == 0; }
+
+const ZVariant *find_variant(int R, const stencil_tile &t)
+{
+    for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
+        const ZVariant *v = p1310::zmarch_variant(i);
+        if (v->R == R && v->bx == t.bx && v->by == t.by && v->ry == t.ry && v->vw == t.vw && v->pf == t.pf)
+            return v;
+    }
+    return nullptr;
+}
+
+// Checks a concrete tile against the grid; on success fills *norm with the
+// normalised tile (vw picked, xcd clamped).
+stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile *norm)
+{
+    stencil_tile t = in;
+    const stencil_desc &d = ctx->d;
+    if (t.kind == STENCIL_TILE_PLAIN) {
+        if (t.bx < 1 || t.by < 1 || t.dz < 1 || (int64_t)t.bx * t.by * t.dz > 1024)
+            return fail(ctx, STENCIL_EUNSUPPORTED, "plain tile needs bx, by, dz >= 1 and bx*by*dz <= 1024");
+        if ((d.ny + t.by - 1) / t.by > 65535 || (d.nz + t.dz - 1) / t.dz > 65535 ||
+            (d.nx + t.bx - 1) / t.bx > 0x7fffffff)
+            return fail(ctx, STENCIL_EUNSUPPORTED, "plain tile: launch grid too large for this grid");
+        t.ry = 1;
+        t.vw = 1;
+        t.xcd = 0;
+        t.pf = 0;
+        *norm = t;
+        return STENCIL_OK;
+    }
+    if (t.kind != STENCIL_TILE_ZMARCH) return fail(ctx, STENCIL_EUNSUPPORTED, "unknown tile kind");
+    if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
+    if (t.vw == 4 && !vec4_ok(ctx))
+        return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
+    if (!find_variant(ctx->R, t))
+        return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
+    if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
+    if (t.dz > d.nz) t.dz = (int32_t)d.nz;
+    const int64_t plane_bytes = d.nx * d.ny * 4;
+    if ((t.dz + 2 * ctx->R) * plane_bytes >= kWindowLimit)
+        return fail(ctx, STENCIL_EUNSUPPORTED, "z-march window (dz + 2R planes) must stay below 2 GiB; lower dz");
+    const int64_t gx = (d.nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw);
+    const int64_t gy = (d.ny + (int64_t)t.by * t.ry - 1) / ((int64_t)t.by * t.ry);
+    const int64_t gz = (d.nz + t.dz - 1) / t.dz;
+    if (gx * gy * gz > 0x7fffffff) return fail(ctx, STENCIL_EUNSUPPORTED, "too many workgroups");
+    t.xcd = t.xcd ? kXcds : 0;
+    *norm = t;
+    return STENCIL_OK;
+}
+
+bool zmarch_possible(const stencil_ctx *ctx)
+{
+    return (1 + 2 * ctx->R) * ctx->d.nx * ctx->d.ny * 4 < kWindowLimit;
+}
+
+stencil_tile default_tile(const stencil_ctx *ctx)
+{
+    stencil_tile t = {};
+    if (!zmarch_possible(ctx)) {
+        t.kind = STENCIL_TILE_PLAIN;
+        t.bx = 64;
+        t.by = 4;
+        t.dz = 1;
+        return t;
+    }
+    t.kind = STENCIL_TILE_ZMARCH;
+    if (vec4_ok(ctx)) {
+        t.bx = 16;
+        t.by = 8;
+        t.ry = 2;
+        t.vw = 4;
+    } else {
+        t.bx = 64;
+        t.by = 4;
+        t.ry = 2;
+        t.vw = 1;
+    }
+    t.dz = 64;
+    t.xcd = 1;
+    t.pf = 0;
+    return t;
+}
+
+// --------------------------------------------------------------------------
+// Tune cache: one line per entry,
+//   gfx950 R<r> f32 <nx> <ny> <nz> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms> <actual_ms>
+// The last matching line wins.
+// --------------------------------------------------------------------------
+bool cache_lookup(const char *path, const stencil_ctx *ctx, stencil_tile *t, double *mn, double *act)
+{
+    if (!path || !*path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[32], rr[8], dt[8];
+        long long nx, ny, nz;
+        stencil_tile c = {};
+        double a = 0, b = 0;
+        int n = std::sscanf(line, "%31s %7s %7s %lld %lld %lld %d %d %d %d %d %d %d %d %lf %lf", arch, rr, dt, &nx, &ny,
+                            &nz, &c.kind, &c.bx, &c.by, &c.ry, &c.dz, &c.vw, &c.xcd, &c.pf, &a, &b);
+        if (n != 16) continue;
+        char want[8];
+        std::snprintf(want, sizeof want, "R%d", ctx->R);
+        if (std::strcmp(arch, "gfx950") || std::strcmp(rr, want) || std::strcmp(dt, "f32")) continue;
+        if (nx != ctx->d.nx || ny != ctx->d.ny || nz != ctx->d.nz) continue;
+        *t = c;
+        *mn = a;
+        *act = b;
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const stencil_ctx *ctx, const stencil_tile &t, double mn, double act)
+{
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "gfx950 R%d f32 %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", ctx->R,
+                 (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, t.kind, t.bx, t.by, t.ry, t.dz,
+                 t.vw, t.xcd, t.pf, mn, act);
+    std::fclose(f);
+}
+
+bool overlaps(const void *a, const void *b, int64_t bytes)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + (uintptr_t)bytes && y < x + (uintptr_t)bytes;
+}
+
+// Makes ctx->d.device current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t status = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        status = hipGetDevice(&prev);
+        if (status == hipSuccess && prev != dev) status = hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+stencil_status hip_fail(stencil_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, STENCIL_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Enqueue one step with a given (already checked) tile.
+hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const float *kappa, const float *ucur,
+                        float *uprev, int64_t it, const stencil_src *src, hipStream_t s)
+{
+    const stencil_desc &d = ctx->d;
+    SweepArgs a = {};
+    a.kappa = kappa;
+    a.ucur = ucur;
+    a.uprev = uprev;
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    for (int m = 0; m <= ctx->R; ++m) a.c[m] = ctx->cf[m];
+    const int nsrc = src ? src->n : 0;
+    a.nsrc = (nsrc == 1) ? 1 : 0;
+    a.src_idx = nsrc == 1 ? src->idx : nullptr;
+    a.src_amp = nsrc == 1 ? src->amp : nullptr;
+    a.it = it;
+    hipError_t e;
+    if (t.kind == STENCIL_TILE_PLAIN) {
+        e = p1310::launch_plain(ctx->R, t.bx, t.by, t.dz, a, s);
+    } else {
+        const ZVariant *v = find_variant(ctx->R, t);
+        if (!v) return hipErrorInvalidValue;
+        a.dz = t.dz;
+        a.gx = (int)((d.nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw));
+        a.gy = (int)((d.ny + (int64_t)t.by * t.ry - 1) / ((int64_t)t.by * t.ry));
+        a.gz = (int)((d.nz + t.dz - 1) / t.dz);
+        a.xcd = t.xcd;
+        e = p1310::launch_zmarch(*v, a, s);
+    }
+    if (e != hipSuccess) return e;
+    if (nsrc > 1) e = p1310::launch_inject(uprev, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, s);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// Candidate tiles of the search.
+// ---------------------------------------------------------------------------
+bool same_tile(const stencil_tile &a, const stencil_tile &b)
+{
+    return a.kind == b.kind && a.bx == b.bx && a.by == b.by && a.ry == b.ry && a.dz == b.dz && a.vw == b.vw &&
+           a.xcd == b.xcd && a.pf == b.pf;
+}
+
+void push_unique(stencil_ctx *ctx, std::vector<stencil_tile> &out, const stencil_tile &t)
+{
+    stencil_tile norm;
+    std::string keep = ctx->err;
+    if (check_tile(ctx, t, &norm) != STENCIL_OK) {
+        ctx->err = keep;
+        return;
+    }
+    for (const auto &o : out)
+        if (same_tile(o, norm)) return;
+    out.push_back(norm);
+}
+
+int64_t snap(int64_t v, const std::vector<int64_t> &legal)
+{
+    int64_t best = legal[0];
+    for (int64_t l : legal)
+        if (std::llabs(l - v) < std::llabs(best - v)) best = l;
+    return best;
+}
+
+std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_opts &o)
+{
+    std::vector<stencil_tile> out;
+    const stencil_desc &d = ctx->d;
+    const int vw = vec4_ok(ctx) ? 4 : 1;
+    std::vector<const ZVariant *> vars;
+    for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
+        const ZVariant *v = p1310::zmarch_variant(i);
+        if (v->R == ctx->R && v->vw == vw) vars.push_back(v);
+    }
+    if (zmarch_possible(ctx) && !vars.empty()) {
+        if (o.parts < 2) {
+            // Every compiled tile shape x a list of z-march depths x XCD order on/off.
+            std::vector<int64_t> dzs = {16, 32, 64, 128, 256};
+            dzs.push_back(d.nz);
+            for (const ZVariant *v : vars)
+                for (int64_t dz : dzs) {
+                    if (dz > d.nz) continue;
+                    for (int xcd = 1; xcd >= 0; --xcd) {
+                        stencil_tile t = {STENCIL_TILE_ZMARCH, v->bx, v->by, v->ry, (int32_t)dz, v->vw, xcd, v->pf};
+                        push_unique(ctx, out, t);
+                    }
+                }
+        } else {
+            // The paper's P-part grid over the three block extents
+            // (tile width, tile height, march depth), each snapped to the
+            // nearest extent a compiled kernel provides.
+            std::vector<int64_t> ltx, lty;
+            for (const ZVariant *v : vars) {
+                ltx.push_back((int64_t)v->bx * v->vw);
+                lty.push_back((int64_t)v->by * v->ry);
+            }
+            std::vector<int64_t> bi(o.parts), bj(o.parts), bk(o.parts);
+            bi.resize(stencil_pgrid(d.nx, o.parts, bi.data(), o.parts));
+            bj.resize(stencil_pgrid(d.ny, o.parts, bj.data(), o.parts));
+            bk.resize(stencil_pgrid(d.nz, o.parts, bk.data(), o.parts));
+            for (int64_t a : bi)
+                for (int64_t b : bj)
+                    for (int64_t c : bk) {
+                        const int64_t tx = snap(a, ltx), ty = snap(b, lty);
+                        for (const ZVariant *v : vars)
+                            if ((int64_t)v->bx * v->vw == tx && (int64_t)v->by * v->ry == ty) {
+                                stencil_tile t = {STENCIL_TILE_ZMARCH, v->bx, v->by, v->ry, (int32_t)c, v->vw, 1, v->pf};
+                                push_unique(ctx, out, t);
+                            }
+                    }
+        }
+    }
+    if (o.include_plain || out.empty()) {
+        const int shapes[][3] = {{64, 4, 1}, {64, 2, 2}, {32, 8, 1}, {128, 2, 1}, {256, 1, 1}, {64, 4, 4}, {32, 4, 8}};
+        for (const auto &sh : shapes) {
+            stencil_tile t = {STENCIL_TILE_PLAIN, sh[0], sh[1], 1, sh[2], 1, 0, 0};
+            push_unique(ctx, out, t);
+        }
+    }
+    return out;
+}
+
+// Time `steps` steps of a tile (after `warm` untimed ones) on the stream;
+// returns milliseconds, or +inf if a launch failed.
+double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, float *&a, float *&b, int warm,
+                 int steps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipError_t *err)
+{
+    for (int i = 0; i < warm; ++i) {
+        hipError_t e = enqueue_step(ctx, t, kappa, a, b, 0, nullptr, s);
+        if (e != hipSuccess) {
+            *err = e;
+            return std::numeric_limits<double>::infinity();
+        }
+        std::swap(a, b);
+    }
+    hipEventRecord(e0, s);
+    for (int i = 0; i < steps; ++i) {
+        hipError_t e = enqueue_step(ctx, t, kappa, a, b, 0, nullptr, s);
+        if (e != hipSuccess) {
+            *err = e;
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            return std::numeric_limits<double>::infinity();
+        }
+        std::swap(a, b);
+    }
+    hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e != hipSuccess) {
+        *err = e;
+        return std::numeric_limits<double>::infinity();
+    }
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *stencil_strerror(stencil_status s)
+{
+    switch (s) {
+    case STENCIL_OK: return "success";
+    case STENCIL_EINVAL: return "invalid argument";
+    case STENCIL_EUNSTABLE: return "time step above the leapfrog stability limit";
+    case STENCIL_ENOMEM: return "out of host memory";
+    case STENCIL_EDEVICE: return "HIP device error";
+    case STENCIL_EUNSUPPORTED: return "unsupported storage type or tile";
+    case STENCIL_EALIAS: return "u_cur and u_prev_next overlap";
+    }
+    return "unknown status";
+}
+
+const char *stencil_last_error(const stencil_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+double stencil_cfl_limit(int32_t radius) { return radius_ok(radius) ? cfl_limit_of(radius) : -1.0; }
+
+int32_t stencil_coefficients(int32_t radius, float *out)
+{
+    if (!radius_ok(radius) || !out) return STENCIL_EINVAL;
+    Rat c[p1310::kMaxRadius + 1];
+    weights(radius, c);
+    out[0] = (float)rat_to_double(rmul(c[0], 3));
+    for (int m = 1; m <= radius; ++m) out[m] = (float)rat_to_double(c[m]);
+    return radius + 1;
+}
+
+stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
+{
+    if (!d || !out) return STENCIL_EINVAL;
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 0x7fffffff || d->ny > 0x7fffffff || d->nz > 0x7fffffff)
+        return STENCIL_EINVAL;
+    if (d->nx * d->ny > ((int64_t)1 << 29)) return STENCIL_EINVAL;  // plane byte offsets are 32-bit
+    if (!radius_ok(d->radius)) return STENCIL_EINVAL;
+    if (d->storage != STENCIL_F32) return STENCIL_EUNSUPPORTED;
+    if (!(d->h > 0) || !(d->dt > 0) || !(d->vmax > 0) || !std::isfinite(d->h) || !std::isfinite(d->dt) ||
+        !std::isfinite(d->vmax))
+        return STENCIL_EINVAL;
+    if (d->device < 0) return STENCIL_EINVAL;
+    if (d->vmax * d->dt / d->h > cfl_limit_of(d->radius)) return STENCIL_EUNSTABLE;
+    stencil_ctx *ctx = new (std::nothrow) stencil_ctx;
+    if (!ctx) return STENCIL_ENOMEM;
+    ctx->d = *d;
+    ctx->R = d->radius;
+    stencil_coefficients(ctx->R, ctx->cf);
+    stencil_tile t = default_tile(ctx);
+    if (d->tile.kind != STENCIL_TILE_AUTO) {
+        t = d->tile;
+    } else {
+        double mn, act;
+        stencil_tile c;
+        if (cache_lookup(std::getenv("STENCIL_TUNE_CACHE"), ctx, &c, &mn, &act)) t = c;
+    }
+    stencil_tile norm;
+    stencil_status st = check_tile(ctx, t, &norm);
+    if (st != STENCIL_OK && d->tile.kind == STENCIL_TILE_AUTO)
+        st = check_tile(ctx, default_tile(ctx), &norm);  // bad cache entry: fall back
+    if (st != STENCIL_OK) {
+        delete ctx;
+        return st;
+    }
+    ctx->tile = norm;
+    *out = ctx;
+    return STENCIL_OK;
+}
+
+void stencil_destroy(stencil_ctx *ctx) { delete ctx; }
+
+stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out)
+{
+    if (!ctx || !out) return STENCIL_EINVAL;
+    *out = ctx->tile;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile)
+{
+    if (!ctx || !tile) return STENCIL_EINVAL;
+    stencil_tile norm;
+    stencil_tile t = *tile;
+    if (t.kind == STENCIL_TILE_AUTO) t = default_tile(ctx);
+    stencil_status st = check_tile(ctx, t, &norm);
+    if (st != STENCIL_OK) return st;
+    ctx->tile = norm;
+    return STENCIL_OK;
+}
+
+int32_t stencil_list_tiles(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap)
+{
+    if (!radius_ok(radius) || cap < 0) return STENCIL_EINVAL;
+    int32_t n = 0;
+    for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
+        const ZVariant *v = p1310::zmarch_variant(i);
+        if (v->R != radius || v->vw != (vec4 ? 4 : 1)) continue;
+        if (out && n < cap) {
+            stencil_tile t = {};
+            t.kind = STENCIL_TILE_ZMARCH;
+            t.bx = v->bx;
+            t.by = v->by;
+            t.ry = v->ry;
+            t.vw = v->vw;
+            t.pf = v->pf;
+            out[n] = t;
+        }
+        ++n;
+    }
+    return n;
+}
+
+stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!v || !kappa) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = p1310::launch_kappa((const float *)v, (float *)kappa, npoints(ctx), ctx->d.dt, ctx->d.h,
+                                       (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kappa launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur, void *u_prev_next, int64_t it,
+                            const stencil_src *src, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!kappa || !u_cur || !u_prev_next) return fail(ctx, STENCIL_EINVAL, "null field pointer");
+    const int64_t bytes = npoints(ctx) * 4;
+    if (overlaps(u_cur, u_prev_next, bytes)) return fail(ctx, STENCIL_EALIAS, "u_cur overlaps u_prev_next");
+    if (overlaps(kappa, u_prev_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps u_prev_next");
+    if (ctx->tile.vw == 4 &&
+        (((uintptr_t)kappa | (uintptr_t)u_cur | (uintptr_t)u_prev_next) & 15u))
+        return fail(ctx, STENCIL_EINVAL, "fields must be 16-byte aligned for vw = 4");
+    if (src && src->n != 0) {
+        if (src->n < 0 || !src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
+        if (it < 0 || it >= src->nt) return fail(ctx, STENCIL_EINVAL, "step index outside the source's samples");
+    }
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = enqueue_step(ctx, ctx->tile, (const float *)kappa, (const float *)u_cur, (float *)u_prev_next, it,
+                                (src && src->n) ? src : nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sweep launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_select(const double *t, int32_t n_nodes, int32_t n_cores, int32_t n_cand, int32_t policy,
+                              int32_t *best_id, double *best_time)
+{
+    if (!t || !best_id || !best_time || n_nodes < 1 || n_cores < 1 || n_cand < 1) return STENCIL_EINVAL;
+    if (policy < STENCIL_POLICY_WORST || policy > STENCIL_POLICY_OB) return STENCIL_EINVAL;
+    auto at = [&](int i, int k, int j) { return t[((int64_t)i * n_cores + k) * n_cand + j]; };
+    if (policy == STENCIL_POLICY_OB) {
+        int bi = 0, bj = 0;
+        double bt = at(0, 0, 0);
+        for (int i = 0; i < n_nodes; ++i)
+            for (int k = 0; k < n_cores; ++k)
+                for (int j = 0; j < n_cand; ++j)
+                    if (at(i, k, j) < bt) {
+                        bt = at(i, k, j);
+                        bi = i;
+                        bj = j;
+                    }
+        *best_id = bi * n_cand + bj;
+        *best_time = bt;
+        return STENCIL_OK;
+    }
+    double node_t = 0;
+    int node_id = -1;
+    std::vector<int> win(n_cores);
+    std::vector<double> wt(n_cores);
+    for (int i = 0; i < n_nodes; ++i) {
+        // Stage 1: every core keeps its fastest candidate (first on ties).
+        for (int k = 0; k < n_cores; ++k) {
+            int bj = 0;
+            for (int j = 1; j < n_cand; ++j)
+                if (at(i, k, j) < at(i, k, bj)) bj = j;
+            win[k] = bj;
+            wt[k] = at(i, k, bj);
+        }
+        // Stage 2: one core winner per node by the policy (first core on ties).
+        int pick = 0;
+        if (policy == STENCIL_POLICY_MIN) {
+            for (int k = 1; k < n_cores; ++k)
+                if (wt[k] < wt[pick]) pick = k;
+        } else if (policy == STENCIL_POLICY_WORST) {
+            for (int k = 1; k < n_cores; ++k)
+                if (wt[k] > wt[pick]) pick = k;
+        } else {
+            double mean = 0;
+            for (int k = 0; k < n_cores; ++k) mean += wt[k];
+            mean /= n_cores;
+            for (int k = 1; k < n_cores; ++k)
+                if (std::fabs(wt[k] - mean) < std::fabs(wt[pick] - mean)) pick = k;
+        }
+        // Stage 3: the fastest node choice (first node on ties).
+        if (node_id < 0 || wt[pick] < node_t) {
+            node_t = wt[pick];
+            node_id = i * n_cand + win[pick];
+        }
+    }
+    *best_id = node_id;
+    *best_time = node_t;
+    return STENCIL_OK;
+}
+
+int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap)
+{
+    if (S < 1 || P < 2 || cap < 0) return STENCIL_EINVAL;
+    int32_t n = 0;
+    int64_t last = -1;
+    for (int64_t j = 0; j < P; ++j) {
+        int64_t b = 1 + (j * S) / (P - 1);
+        if (b > S) b = S;
+        if (b == last) continue;
+        last = b;
+        if (out && n < cap) out[n] = b;
+        ++n;
+    }
+    return n;
+}
+
+
+stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a, void *scratch_b,
+                            const stencil_tune_opts *opts, stencil_tune_report *report, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!kappa || !scratch_a || !scratch_b || !report) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    const int64_t bytes = npoints(ctx) * 4;
+    if (overlaps(scratch_a, scratch_b, bytes) || overlaps(kappa, scratch_a, bytes) || overlaps(kappa, scratch_b, bytes))
+        return fail(ctx, STENCIL_EALIAS, "kappa and the two scratch fields must not overlap");
+    if (((uintptr_t)kappa | (uintptr_t)scratch_a | (uintptr_t)scratch_b) & 15u)
+        return fail(ctx, STENCIL_EINVAL, "fields must be 16-byte aligned");
+    stencil_tune_opts o = {};
+    if (opts) o = *opts;
+    if (o.policy < STENCIL_POLICY_WORST || o.policy > STENCIL_POLICY_OB) return fail(ctx, STENCIL_EINVAL, "bad policy");
+    if (o.n_iter < 0 || o.n_rep < 0 || o.parts < 0 || o.parts == 1 || o.table_cap < 0)
+        return fail(ctx, STENCIL_EINVAL, "bad tune options");
+    const int n_iter = o.n_iter ? o.n_iter : 10;
+    const int n_rep = o.n_rep ? o.n_rep : 3;
+    const int warm = o.warmup == 0 ? 2 : (o.warmup < 0 ? 0 : o.warmup);
+    *report = stencil_tune_report{};
+    const auto t_start = std::chrono::steady_clock::now();
+
+    {
+        stencil_tile c;
+        double mn, act;
+        if (cache_lookup(o.cache_path, ctx, &c, &mn, &act)) {
+            stencil_tile norm;
+            if (check_tile(ctx, c, &norm) == STENCIL_OK) {
+                ctx->tile = norm;
+                report->tile = norm;
+                report->min_time_ms = mn;
+                report->actual_time_ms = act;
+                report->gap = (act - mn) / mn;
+                report->from_cache = 1;
+                report->n_candidates = 0;
+                return STENCIL_OK;
+            }
+        }
+    }
+
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<stencil_tile> cands = make_candidates(ctx, o);
+    const int nC = (int)cands.size();
+    if (nC == 0) return fail(ctx, STENCIL_EUNSUPPORTED, "no candidate tile fits this grid");
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipEventCreate");
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(ctx, he, "hipEventCreate");
+    }
+    float *a = (float *)scratch_a, *b = (float *)scratch_b;
+    const float *k = (const float *)kappa;
+    std::vector<double> table((size_t)n_rep * nC, std::numeric_limits<double>::infinity());
+    hipError_t last = hipSuccess;
+
+    // Selection phase: every replicate times every candidate in the same order.
+    for (int r = 0; r < n_rep; ++r)
+        for (int c = 0; c < nC; ++c) {
+            hipError_t e = hipSuccess;
+            table[(size_t)r * nC + c] = time_tile(ctx, cands[c], k, a, b, warm, n_iter, s, e0, e1, &e);
+            if (e != hipSuccess) last = e;
+        }
+    bool any = false;
+    for (double v : table) any = any || std::isfinite(v);
+    if (!any) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return hip_fail(ctx, last == hipSuccess ? hipErrorLaunchFailure : last, "every candidate failed");
+    }
+    int32_t best = 0;
+    double min_time = 0;
+    stencil_select(table.data(), 1, n_rep, nC, o.policy, &best, &min_time);
+
+    // Verification phase: the chosen tile again, then the default for context.
+    hipError_t e = hipSuccess;
+    const double actual = time_tile(ctx, cands[best], k, a, b, warm, n_iter, s, e0, e1, &e);
+    stencil_tile dflt;
+    double dtime = std::numeric_limits<double>::infinity();
+    if (check_tile(ctx, default_tile(ctx), &dflt) == STENCIL_OK)
+        dtime = time_tile(ctx, dflt, k, a, b, warm, n_iter, s, e0, e1, &e);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!std::isfinite(actual)) return hip_fail(ctx, e, "verification run failed");
+
+    ctx->tile = cands[best];
+    report->tile = cands[best];
+    report->min_time_ms = min_time;
+    report->actual_time_ms = actual;
+    report->gap = (actual - min_time) / min_time;
+    report->default_time_ms = dtime;
+    report->n_candidates = nC;
+    report->from_cache = 0;
+    report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (o.table && o.table_cap > 0)
+        for (int r = 0; r < n_rep; ++r)
+            for (int c = 0; c < nC && c < o.table_cap; ++c) o.table[(size_t)r * o.table_cap + c] = table[(size_t)r * nC + c];
+    if (o.candidates)
+        for (int c = 0; c < nC && c < o.table_cap; ++c) o.candidates[c] = cands[c];
+    cache_store(o.cache_path, ctx, cands[best], min_time, actual);
+    return STENCIL_OK;
+}
+
+stencil_status stencil_copy_probe(const void *src, void *dst, int64_t nbytes, void *stream)
+{
+    if (!src || !dst || nbytes <= 0 || nbytes % 16 || (((uintptr_t)src | (uintptr_t)dst) & 15u))
+        return STENCIL_EINVAL;
+    hipError_t e = p1310::launch_copy(src, dst, nbytes, (hipStream_t)stream);
+    return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Internal interface between the C-ABI runtime (api.cpp) and the gfx950
+// kernels (kernels.hip). Not installed; the public interface is
+// include/stencil.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace p1310 {
+
+constexpr int kMaxRadius = 5;
+
+// Arguments of one sweep launch (passed by value as the kernel argument).
+struct SweepArgs {
+    const float *kappa;      // [nz][ny][nx]
+    const float *ucur;       // u^n
+    float *uprev;            // u^{n-1} on entry, u^{n+1} on exit
+    int nx, ny, nz;
+    int dz;                  // planes per workgroup (z-march)
+    int gx, gy, gz;          // tiles along x, y and z-chunks
+    int xcd;                 // 0 = linear workgroup order, else number of XCDs to spread over
+    float c[kMaxRadius + 1]; // c[0] = 3*c_0, c[m] = c_m
+    const int64_t *src_idx;  // fused single source (nsrc == 1), else unused
+    const float *src_amp;
+    int nsrc;
+    int64_t it;
+};
+
+// One compiled z-march instantiation.
+struct ZVariant {
+    int R, bx, by, ry, vw, pf;
+    void (*kernel)(SweepArgs);
+    int threads;
+    int lds_bytes;
+};
+
+// Registry of compiled z-march kernels (kernels.hip).
+int zmarch_variant_count();
+const ZVariant *zmarch_variant(int i);
+
+// Launchers (kernels.hip). All enqueue on `s` and return the launch status.
+hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s);
+hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
+hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
+                         const float *amp, int nsrc, int64_t it, hipStream_t s);
+hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, double h, hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+
+}  // namespace p1310

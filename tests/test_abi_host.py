@@ -1,0 +1,164 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared entry
+point, and its host-only logic (argument validation, the blocksize-selection
+rule, the P-part grid, weights, stability limit) agrees with the oracle. No
+call here launches a kernel."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_8232_amd as p
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_library_agree():
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(p._lib, n), f"library does not export {n}"
+    assert set(names) == set(p.EXPORTED)
+
+
+def test_strerror_covers_codes():
+    for code in (p.OK, p.EINVAL, p.EUNSTABLE, p.ENOMEM, p.EDEVICE, p.EUNSUPPORTED, p.EALIAS):
+        assert p.stencil_strerror(code) not in ("", "unknown status")
+
+
+@pytest.mark.parametrize("R", [3, 4, 5])
+def test_weights_match_oracle(R):
+    c = oracle.fd_coefficients(R)
+    got = p.stencil_coefficients(R)
+    assert len(got) == R + 1
+    assert got[0] == np.float32(3.0 * c[0])
+    for m in range(1, R + 1):
+        assert got[m] == np.float32(c[m])
+
+
+@pytest.mark.parametrize("R", [3, 4, 5])
+def test_cfl_limit_matches_oracle(R):
+    assert abs(p.stencil_cfl_limit(R) - oracle.cfl_limit(R)) < 1e-12
+
+
+def test_pgrid_matches_paper_and_oracle():
+    g = json.load(open(os.path.join(GOLDEN, "pgrid_paper_example.json")))
+    for S, expect in zip(g["S"], g["lists"]):
+        assert p.stencil_pgrid(S, g["P"]) == expect
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        S = int(rng.integers(1, 3000))
+        P = int(rng.integers(2, 25))
+        assert p.stencil_pgrid(S, P) == oracle.pgrid(S, P)
+
+
+@pytest.mark.parametrize("policy", ["worst", "min", "avg", "ob"])
+def test_select_matches_oracle(policy):
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        nn, nk, nc = (int(rng.integers(1, 4)), int(rng.integers(1, 6)), int(rng.integers(1, 7)))
+        t = rng.integers(1, 7, size=(nn, nk, nc)).astype(float)
+        if rng.random() < 0.5:
+            t = t + rng.random(size=t.shape)
+        ids = [list(range(i * nc, (i + 1) * nc)) for i in range(nn)]
+        assert p.stencil_select(t.tolist(), policy) == oracle.select_block(t.tolist(), ids, policy)
+
+
+def _init(**kw):
+    args = dict(nx=32, ny=32, nz=32, h=10.0, dt=0.002, vmax=2000.0)
+    args.update(kw)
+    return p.stencil_init(**args)
+
+
+def test_init_validation():
+    ctx = _init()
+    p.stencil_destroy(ctx)
+    for bad in (dict(nx=0), dict(ny=-1), dict(h=0.0), dict(dt=-1.0), dict(vmax=float("nan")), dict(radius=2),
+                dict(radius=6), dict(device=-1)):
+        with pytest.raises(p.StencilError) as e:
+            _init(**bad)
+        assert e.value.status == p.EINVAL, bad
+    lim = p.stencil_cfl_limit(4)
+    ctx = _init(dt=0.999 * lim * 10.0 / 2000.0)
+    p.stencil_destroy(ctx)
+    with pytest.raises(p.StencilError) as e:
+        _init(dt=1.001 * lim * 10.0 / 2000.0)
+    assert e.value.status == p.EUNSTABLE
+
+
+def test_unsupported_storage():
+    d = p.StencilDesc(16, 16, 16, 4, 7, 10.0, 0.001, 2000.0, 0, p.StencilTile())
+    out = ctypes.c_void_p()
+    assert p._lib.stencil_init(ctypes.byref(d), ctypes.byref(out)) == p.EUNSUPPORTED
+
+
+def test_tiles_default_set_and_reject():
+    ctx = _init(nx=64, ny=48, nz=40)
+    t = p.stencil_get_tile(ctx)
+    assert t.kind == p.TILE_ZMARCH and t.vw == 4 and t.dz >= 1
+    tiles = p.stencil_list_tiles(4, True)
+    assert len(tiles) >= 10
+    for tt in tiles:
+        tt.dz = 16
+        p.stencil_set_tile(ctx, tt)
+        got = p.stencil_get_tile(ctx)
+        assert (got.bx, got.by, got.ry, got.vw, got.pf, got.dz) == (tt.bx, tt.by, tt.ry, tt.vw, tt.pf, 16)
+    before = p.stencil_get_tile(ctx)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, p.make_tile(bx=7, by=3, ry=1, dz=8, vw=4))
+    assert e.value.status == p.EUNSUPPORTED
+    assert p.stencil_get_tile(ctx).as_dict() == before.as_dict()
+    with pytest.raises(p.StencilError):
+        p.stencil_set_tile(ctx, p.make_tile(p.TILE_PLAIN, bx=64, by=32, dz=1))  # 2048 threads
+    p.stencil_set_tile(ctx, p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=2))
+    p.stencil_destroy(ctx)
+    # nx % 4 != 0: vector tiles are refused, the default falls back to vw = 1.
+    ctx = _init(nx=61, ny=45, nz=37)
+    assert p.stencil_get_tile(ctx).vw == 1
+    with pytest.raises(p.StencilError):
+        p.stencil_set_tile(ctx, p.make_tile(bx=16, by=8, ry=2, dz=16, vw=4))
+    p.stencil_destroy(ctx)
+
+
+def test_step_argument_errors_before_launch():
+    # Validation runs before any HIP call, so fake pointers exercise it on the CPU.
+    ctx = _init(nx=16, ny=16, nz=16)
+    n = 16 ** 3 * 4
+    base = 1 << 40
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base, base + 2 * n, base + 2 * n + 64, 0, None, 0)
+    assert e.value.status == p.EALIAS
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base + 2 * n, base, base + n // 2, 0, None, 0)
+    assert e.value.status == p.EALIAS
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base, base + 4 * n + 4, base + 8 * n, 0, None, 0)
+    assert e.value.status == p.EINVAL  # misaligned for vw = 4
+    src = p.StencilSrc(1, base + 64 * n, base + 65 * n, 5)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base, base + 2 * n, base + 4 * n, 5, src, 0)
+    assert e.value.status == p.EINVAL  # it >= nt
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, 0, base + 2 * n, base + 4 * n, 0, None, 0)
+    assert e.value.status == p.EINVAL
+    assert "null" in p.stencil_last_error(ctx)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_tune(ctx, base, base, base + 4 * n, stream=0)
+    assert e.value.status == p.EALIAS
+    p.stencil_destroy(ctx)
+
+
+def test_copy_probe_validation():
+    with pytest.raises(p.StencilError):
+        p.stencil_copy_probe(1 << 40, (1 << 40) + 4096, 100, stream=0)

@@ -1,0 +1,263 @@
+"""GPU parity: the gfx950 path (through the C ABI) against the FP64 oracle.
+
+Bars: relative L2 <= 1e-5 per output against the FP64 oracle (FP32 storage and
+arithmetic); bit-identical outputs across every tile shape, march depth, XCD
+order and the plain-tiling kernel (all use one canonical FP32 operation
+order); kappa bit-identical to the FP64 formula rounded once.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_1310_8232_amd as p
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def cuda(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dtype)
+
+
+def gpu_run(v, h, dt, vmax, R, nt, u0=None, um1=None, src_idx=None, amp=None, tile=None, it0=0):
+    prop = p.Propagator(cuda(v), h, dt, R, vmax=vmax, tile=tile)
+    shape = v.shape
+    a = cuda(u0) if u0 is not None else torch.zeros(shape, device="cuda:0")
+    b = cuda(um1) if um1 is not None else torch.zeros(shape, device="cuda:0")
+    src = None
+    keep = None
+    if src_idx is not None:
+        idx_t = cuda(np.asarray(src_idx, np.int64), torch.int64)
+        amp_t = cuda(np.asarray(amp, np.float32).reshape(len(amp), -1))
+        keep = (idx_t, amp_t)
+        src = p.make_src(idx_t, amp_t)
+    a, b = prop.run(a, b, nt, src, it0=it0)
+    torch.cuda.synchronize()
+    del keep
+    return a.cpu().numpy(), b.cpu().numpy(), prop
+
+
+def oracle_run(v, h, dt, R, nt, u0=None, um1=None, src_idx=None, amp=None, it0=0):
+    kap = oracle.kappa(v, dt, h)
+    z = np.zeros(v.shape)
+    return oracle.leapfrog(kap, z if u0 is None else u0, z if um1 is None else um1, R, nt, it0=it0,
+                           src_idx=src_idx, amp=None if amp is None else np.asarray(amp, np.float64))
+
+
+def assert_close(got, ref, tol=TOL, what=""):
+    e = oracle.rel_l2(got, ref)
+    log(f"  {what} rel_l2 = {e:.3e}")
+    assert np.all(np.isfinite(got))
+    assert e <= tol, f"{what}: rel_l2 {e:.3e} > {tol:.1e}"
+
+
+def test_kappa_bit_exact():
+    v = workloads.layered_model(33, 20, 17, seed=5)
+    dt, vmax = workloads.dt_for_courant(v, 10.0)
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    got = prop.kappa.cpu().numpy()
+    ref = oracle.kappa(v, dt, 10.0).astype(np.float32)
+    assert np.array_equal(got, ref)
+
+
+def test_plain_method_64cube_100_steps():
+    c = workloads.config_plain()
+    log(f"case: {c['name']} R=4 100 steps, default tile")
+    ref_n, ref_nm1 = oracle_run(c["v"], c["h"], c["dt"], 4, 100, src_idx=c["src_idx"], amp=c["amp"])
+    un, unm1, prop = gpu_run(c["v"], c["h"], c["dt"], c["vmax"], 4, 100, src_idx=c["src_idx"], amp=c["amp"])
+    log(f"  tile {prop.tile}")
+    assert_close(un, ref_n, what="u^100")
+    assert_close(unm1, ref_nm1, what="u^99")
+    # The plain-tiling kernel gives the same bits.
+    pn, pnm1, _ = gpu_run(c["v"], c["h"], c["dt"], c["vmax"], 4, 100, src_idx=c["src_idx"], amp=c["amp"],
+                          tile=p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1))
+    assert np.array_equal(pn, un) and np.array_equal(pnm1, unm1)
+
+
+@pytest.mark.parametrize("R", [3, 4, 5])
+def test_layered_128cube_100_steps(R):
+    c = workloads.config_layered(128, 128, 128, nt=100, radius=R)
+    log(f"case: {c['name']} R={R} 100 steps")
+    ref_n, ref_nm1 = oracle_run(c["v"], c["h"], c["dt"], R, 100, src_idx=c["src_idx"], amp=c["amp"])
+    un, unm1, _ = gpu_run(c["v"], c["h"], c["dt"], c["vmax"], R, 100, src_idx=c["src_idx"], amp=c["amp"])
+    assert_close(un, ref_n, what="u^100")
+    assert_close(unm1, ref_nm1, what="u^99")
+
+
+def _random_case(nx, ny, nz, seed, R=4):
+    v = workloads.layered_model(nx, ny, nz, seed=seed)
+    dt, vmax = workloads.dt_for_courant(v, 10.0)
+    u0 = workloads.random_field(nx, ny, nz, seed + 1)
+    um1 = workloads.random_field(nx, ny, nz, seed + 2)
+    return v, dt, vmax, u0, um1
+
+
+def _tiles(R, vec4, dzs):
+    out = []
+    for t in p.stencil_list_tiles(R, vec4):
+        for dz in dzs:
+            for xcd in (1, 0):
+                out.append(p.make_tile(p.TILE_ZMARCH, t.bx, t.by, t.ry, dz, t.vw, xcd, t.pf))
+    for sh in ((64, 4, 1), (32, 8, 2), (8, 8, 8), (128, 1, 1)):
+        out.append(p.make_tile(p.TILE_PLAIN, bx=sh[0], by=sh[1], dz=sh[2]))
+    return out
+
+
+@pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (3, (72, 45, 37)), (5, (72, 45, 37)),
+                                     (4, (61, 45, 37)), (5, (61, 29, 23)), (4, (260, 67, 19))])
+def test_tile_invariance_and_oracle(R, shape):
+    nx, ny, nz = shape
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=100 + R, R=R)
+    nsteps = 6
+    log(f"case: random fields {nx}x{ny}x{nz} R={R}, {nsteps} steps, every tile")
+    ref_n, ref_nm1 = oracle_run(v, 10.0, dt, R, nsteps, u0, um1)
+    base = None
+    tiles = _tiles(R, nx % 4 == 0, (1, 7, 16, nz))
+    for t in tiles:
+        un, unm1, _ = gpu_run(v, 10.0, dt, vmax, R, nsteps, u0, um1, tile=t)
+        if base is None:
+            base = (un, unm1, t)
+            assert_close(un, ref_n, what=f"u^n {t}")
+            assert_close(unm1, ref_nm1, what=f"u^n-1 {t}")
+        else:
+            assert np.array_equal(un, base[0]), f"tile {t} differs from {base[2]}"
+            assert np.array_equal(unm1, base[1]), f"tile {t} differs from {base[2]}"
+    log(f"  {len(tiles)} tiles bit-identical")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (4, 1, 9), (9, 1, 1), (8, 8, 1), (1, 17, 3),
+                                   (5, 4, 2), (12, 2, 30)])
+def test_degenerate_grids(shape):
+    nx, ny, nz = shape
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=7)
+    log(f"case: degenerate grid {shape}")
+    ref_n, ref_nm1 = oracle_run(v, 10.0, dt, 4, 4, u0, um1)
+    for t in (None, p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1)):
+        un, unm1, _ = gpu_run(v, 10.0, dt, vmax, 4, 4, u0, um1, tile=t)
+        assert_close(un, ref_n, what=f"u^n {shape}")
+        assert_close(unm1, ref_nm1, what=f"u^n-1 {shape}")
+
+
+def test_several_sources_and_out_of_range_index():
+    nx, ny, nz = 40, 36, 30
+    v, dt, vmax, _, _ = _random_case(nx, ny, nz, seed=21)
+    n = nx * ny * nz
+    a_idx, b_idx = (10 * ny + 12) * nx + 7, (25 * ny + 3) * nx + 39
+    nt = 20
+    amp3 = np.stack([workloads.ricker(nt, dt, 25.0), -workloads.ricker(nt, dt, 20.0),
+                     0.5 * workloads.ricker(nt, dt, 30.0)], axis=1)
+    log("case: three sources (one repeated) plus one index outside the grid")
+    ref_n, ref_nm1 = oracle_run(v, 10.0, dt, 4, nt, src_idx=[a_idx, b_idx, a_idx], amp=amp3)
+    amp4 = np.concatenate([amp3, np.ones((nt, 1), np.float32)], axis=1)
+    un, unm1, _ = gpu_run(v, 10.0, dt, vmax, 4, nt, src_idx=[a_idx, b_idx, a_idx, n + 5], amp=amp4)
+    assert_close(un, ref_n, what="u^n")
+    assert_close(unm1, ref_nm1, what="u^n-1")
+
+
+def test_tune_selection_follows_rule_and_cache(tmp_path):
+    nx, ny, nz = 96, 64, 48
+    v, dt, vmax, _, _ = _random_case(nx, ny, nz, seed=31)
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    log("case: tune 96x64x48, full candidate list, 3 replicates")
+    rep, table, cands = prop.tune(n_iter=4, n_rep=3, table_cap=1024, include_plain=True)
+    log(f"  nC={rep['n_candidates']} chosen={rep['tile']} min={rep['min_time_ms']:.4f} "
+        f"actual={rep['actual_time_ms']:.4f} gap={rep['gap']:+.3f} s={rep['seconds']:.2f}")
+    assert rep["n_candidates"] == len(cands) > 10
+    ids = [list(range(len(cands)))]
+    best, t = oracle.select_block([table], ids, "worst")
+    assert cands[best] == rep["tile"]
+    assert t == rep["min_time_ms"]
+    assert abs(rep["gap"] - oracle.gap(rep["min_time_ms"], rep["actual_time_ms"])) < 1e-12
+    assert prop.tile.as_dict() == rep["tile"]
+    # Cache round trip.
+    cache = str(tmp_path / "tune.txt")
+    rep1, _, _ = prop.tune(n_iter=2, n_rep=1, parts=3, cache_path=cache)
+    rep2, _, _ = prop.tune(n_iter=2, n_rep=1, parts=3, cache_path=cache)
+    assert not rep1["from_cache"] and rep2["from_cache"]
+    assert rep2["tile"] == rep1["tile"]
+    assert 0 < rep1["n_candidates"] <= 27 * 8
+
+
+def test_graph_capture_replays_match_eager():
+    nx, ny, nz = 64, 48, 40
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=41)
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    amp = cuda(workloads.ricker(8, dt, 25.0).reshape(8, 1))
+    idx = cuda(np.array([workloads.centre_index(nx, ny, nz)], np.int64), torch.int64)
+    src = p.make_src(idx, amp)
+    a0, b0 = cuda(u0), cuda(um1)
+    a, b = a0.clone(), b0.clone()
+    torch.cuda.synchronize()
+    prop.run(a, b, 4, src)
+    torch.cuda.synchronize()
+    eager_a, eager_b = a.clone(), b.clone()
+
+    ga, gb = a0.clone(), b0.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            prop.run(ga, gb, 4, src)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        ga.copy_(a0)
+        gb.copy_(b0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ga, eager_a) and torch.equal(gb, eager_b), f"replay {rep}"
+        _ = (ga * 2).sum().item()  # eager work between replays
+
+
+def test_copy_probe():
+    x = torch.randn(1 << 20, device="cuda:0")
+    y = torch.empty_like(x)
+    p.stencil_copy_probe(x, y, x.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+
+
+@pytest.mark.slow
+def test_full_size_512_tuned_default_plain():
+    nx = ny = nz = 512
+    log("case: 512^3 layered kappa, random fields, 3 steps: tuned, default and plain tiles vs oracle")
+    t0 = time.time()
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=workloads.SEED)
+    log(f"  inputs {time.time() - t0:.1f}s")
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    rep, _, _ = prop.tune(parts=3, n_iter=5, n_rep=2)
+    log(f"  tuned {rep['tile']} nC={rep['n_candidates']} {rep['seconds']:.1f}s")
+    tuned = prop.tile
+    del prop
+    torch.cuda.empty_cache()
+    t0 = time.time()
+    ref_n, ref_nm1 = oracle_run(v, 10.0, dt, 4, 3, u0, um1)
+    log(f"  oracle {time.time() - t0:.1f}s")
+    base = None
+    for t in (tuned, None, p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1)):
+        un, unm1, _ = gpu_run(v, 10.0, dt, vmax, 4, 3, u0, um1, tile=t)
+        torch.cuda.empty_cache()
+        if base is None:
+            base = (un, unm1)
+            assert_close(un, ref_n, what="u^3")
+            assert_close(unm1, ref_nm1, what="u^2")
+        else:
+            assert np.array_equal(un, base[0]) and np.array_equal(unm1, base[1])
