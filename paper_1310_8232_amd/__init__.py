@@ -15,6 +15,12 @@ from __future__ import annotations
 import ctypes
 import os
 
+# torch ships its own HIP runtime (libamdhip64.so.7). Loading it before the
+# library makes the library's libamdhip64.so.7 dependency resolve to that same
+# runtime, so the process holds one HIP runtime and torch tensors, streams and
+# the library's kernels share one device context.
+import torch  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpaper_1310_8232_amd.so")
 
