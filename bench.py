@@ -32,7 +32,7 @@ METRIC = "Gpoint-updates/s + % of HBM roofline, 512^3 8th-order FP32 vs plain ti
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hpp", "kernels_radius.hip"):
+    for f in ("sweep.hpp",):
         with open(os.path.join(ROOT, "paper_1310_8232_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,6 +92,33 @@ def cpu_baseline(cfg, budget_s: float):
                       f"layered workload from rest (source on), {t1 + t2:.1f} s"}
 
 
+def stream_probe(mib: int, n_in: int, steps: int, warmup: int) -> int:
+    """Time the library's streaming reference: n_in inputs of mib MiB read and
+    one of mib MiB written per launch (n_in = 3 is the sweep's traffic mix)."""
+    import torch
+
+    import paper_1310_8232_amd as p
+    nbytes = mib << 20
+    ins = [torch.ones(nbytes // 4, device="cuda:0") for _ in range(n_in)] + [None] * (3 - n_in)
+    out = torch.empty(nbytes // 4, device="cuda:0")
+    for _ in range(warmup):
+        p.stencil_stream_probe(*ins, out, nbytes)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        p.stencil_stream_probe(*ins, out, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    moved = (n_in + 1) * nbytes
+    print(json.dumps({"stream_probe": {"inputs": n_in, "bytes_read": n_in * nbytes, "bytes_written": nbytes,
+                                       "launches": steps, "ms_per_launch": round(ms, 5),
+                                       "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +134,10 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
+                    help="only time the library's streaming reference over MIB MiB arrays")
+    ap.add_argument("--stream-inputs", type=int, default=3, choices=(1, 2, 3),
+                    help="inputs of the streaming reference (1 = copy, 3 = the sweep's read/write mix)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -121,6 +152,8 @@ def main(argv=None):
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.stream_probe:
+        return stream_probe(args.stream_probe, args.stream_inputs, args.steps, args.warmup)
     n = args.n
     nt = args.warmup + args.steps
     t0 = time.perf_counter()

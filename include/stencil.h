@@ -196,9 +196,13 @@ stencil_status stencil_select(const double *t, int32_t n_nodes, int32_t n_cores,
  * Writes at most cap values and returns the count (or EINVAL). */
 int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap);
 
-/* Streaming copy of nbytes (multiple of 16, 16-byte aligned pointers) from
- * src to dst on `stream`: a bandwidth reference for the sweep. */
-stencil_status stencil_copy_probe(const void *src, void *dst, int64_t nbytes, void *stream);
+/* Bandwidth reference: out[i] = a[i] (+ b[i]) (+ c[i]) over nbytes of FP32
+ * (a multiple of 16; 16-byte aligned device pointers; b may be NULL, c may be
+ * NULL, c non-NULL needs b). With b = c = NULL it is a plain copy; with all
+ * three it has the sweep's traffic mix of three reads per write. Enqueued on
+ * `stream`. */
+stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
+                                    void *stream);
 
 /* Message for a status code (static storage). */
 const char *stencil_strerror(stencil_status s);

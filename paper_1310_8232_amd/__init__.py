@@ -95,7 +95,7 @@ _sig = {
     "stencil_select": (_i32, [ctypes.POINTER(ctypes.c_double), _i32, _i32, _i32, _i32,
                               ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "stencil_pgrid": (_i32, [_i64, _i32, ctypes.POINTER(_i64), _i32]),
-    "stencil_copy_probe": (_i32, [_vp, _vp, _i64, _vp]),
+    "stencil_stream_probe": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp]),
     "stencil_strerror": (ctypes.c_char_p, [_i32]),
     "stencil_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -261,8 +261,9 @@ def stencil_pgrid(S: int, P: int):
     return [out[i] for i in range(n)]
 
 
-def stencil_copy_probe(src, dst, nbytes: int, stream=None):
-    _check(_lib.stencil_copy_probe(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
+def stencil_stream_probe(a, b, c, out, nbytes: int, stream=None):
+    """out = a (+ b) (+ c) over nbytes; b and c may be None."""
+    _check(_lib.stencil_stream_probe(_ptr(a), _ptr(b), _ptr(c), _ptr(out), int(nbytes), _stream(stream)))
 
 
 class Propagator:
@@ -288,10 +289,10 @@ class Propagator:
         self.kappa = torch.empty_like(v)
         stencil_kappa(self.ctx, v, self.kappa)
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.stencil_destroy):
         ctx = getattr(self, "ctx", None)
         if ctx:
-            stencil_destroy(ctx)
+            _destroy(ctx)
             self.ctx = None
 
     def _check_field(self, t):

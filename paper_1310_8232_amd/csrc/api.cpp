@@ -754,11 +754,13 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     return STENCIL_OK;
 }
 
-stencil_status stencil_copy_probe(const void *src, void *dst, int64_t nbytes, void *stream)
+stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
+                                    void *stream)
 {
-    if (!src || !dst || nbytes <= 0 || nbytes % 16 || (((uintptr_t)src | (uintptr_t)dst) & 15u))
+    if (!a || !out || (c && !b) || nbytes <= 0 || nbytes % 16 ||
+        (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)out) & 15u))
         return STENCIL_EINVAL;
-    hipError_t e = p1310::launch_copy(src, dst, nbytes, (hipStream_t)stream);
+    hipError_t e = p1310::launch_stream(a, b, c, out, nbytes, (hipStream_t)stream);
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
 }
 

@@ -44,6 +44,6 @@ hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipSt
 hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
                          const float *amp, int nsrc, int64_t it, hipStream_t s);
 hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, double h, hipStream_t s);
-hipError_t launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s);
+hipError_t launch_stream(const void *a, const void *b, const void *c, void *out, int64_t nbytes, hipStream_t s);
 
 }  // namespace p1310

@@ -1,5 +1,5 @@
-// Radius-independent kernels (model set-up, multi-source injection, copy
-// reference) and the registry/launchers over the per-radius objects.
+// Radius-independent kernels (model set-up, multi-source injection, streaming
+// bandwidth reference) and the registry/launchers over the per-radius objects.
 #include "internal.h"
 
 namespace p1310 {
@@ -58,11 +58,37 @@ __global__ void __launch_bounds__(64) inject_kernel(float *u, const float *kappa
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) copy_kernel(const f4 *src, f4 *dst, int64_t n4)
+// Streaming reference: out = a (+ b) (+ c), NIN inputs, one output. Each
+// workgroup streams one contiguous chunk of kStreamChunk 16-byte vectors,
+// four loads per input in flight per thread before the stores, all
+// non-temporal (the fastest of the simple streaming patterns measured on
+// MI355X). NIN = 1 is a copy; NIN = 3 has the sweep's three reads per write.
+constexpr int kStreamUnroll = 4;
+constexpr int64_t kStreamChunk = 4096;
+
+template <int NIN>
+__global__ void __launch_bounds__(256) stream_kernel(const f4 *a, const f4 *b, const f4 *c, f4 *out, int64_t n4)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-        __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
+    const int64_t beg = (int64_t)blockIdx.x * kStreamChunk;
+    const int64_t end = (beg + kStreamChunk < n4) ? beg + kStreamChunk : n4;
+    int64_t i = beg + threadIdx.x;
+    for (; i + (kStreamUnroll - 1) * 256 < end; i += kStreamUnroll * 256) {
+        f4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            v[u] = __builtin_nontemporal_load(&a[i + u * 256]);
+            if (NIN > 1) v[u] += __builtin_nontemporal_load(&b[i + u * 256]);
+            if (NIN > 2) v[u] += __builtin_nontemporal_load(&c[i + u * 256]);
+        }
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) __builtin_nontemporal_store(v[u], &out[i + u * 256]);
+    }
+    for (; i < end; i += 256) {
+        f4 v = __builtin_nontemporal_load(&a[i]);
+        if (NIN > 1) v += __builtin_nontemporal_load(&b[i]);
+        if (NIN > 2) v += __builtin_nontemporal_load(&c[i]);
+        __builtin_nontemporal_store(v, &out[i]);
+    }
 }
 
 }  // namespace
@@ -108,13 +134,18 @@ hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, doub
     return hipGetLastError();
 }
 
-hipError_t launch_copy(const void *src, void *dst, int64_t nbytes, hipStream_t s)
+hipError_t launch_stream(const void *a, const void *b, const void *c, void *out, int64_t nbytes, hipStream_t s)
 {
     const int64_t n4 = nbytes / 16;
-    int64_t blocks = (n4 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const f4 *)src, (f4 *)dst, n4);
+    const int64_t blocks = (n4 + kStreamChunk - 1) / kStreamChunk;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const f4 *fa = (const f4 *)a, *fb = (const f4 *)b, *fc = (const f4 *)c;
+    if (c)
+        hipLaunchKernelGGL(stream_kernel<3>, dim3((unsigned)blocks), dim3(256), 0, s, fa, fb, fc, (f4 *)out, n4);
+    else if (b)
+        hipLaunchKernelGGL(stream_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, s, fa, fb, fc, (f4 *)out, n4);
+    else
+        hipLaunchKernelGGL(stream_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s, fa, fb, fc, (f4 *)out, n4);
     return hipGetLastError();
 }
 

@@ -159,6 +159,8 @@ def test_step_argument_errors_before_launch():
     p.stencil_destroy(ctx)
 
 
-def test_copy_probe_validation():
+def test_stream_probe_validation():
     with pytest.raises(p.StencilError):
-        p.stencil_copy_probe(1 << 40, (1 << 40) + 4096, 100, stream=0)
+        p.stencil_stream_probe(1 << 40, None, None, (1 << 40) + 4096, 100, stream=0)
+    with pytest.raises(p.StencilError):
+        p.stencil_stream_probe(1 << 40, None, (1 << 40) + 8192, (1 << 40) + 4096, 4096, stream=0)

@@ -227,12 +227,15 @@ def test_graph_capture_replays_match_eager():
         _ = (ga * 2).sum().item()  # eager work between replays
 
 
-def test_copy_probe():
-    x = torch.randn(1 << 20, device="cuda:0")
-    y = torch.empty_like(x)
-    p.stencil_copy_probe(x, y, x.numel() * 4)
+def test_stream_probe():
+    x, y, z = (torch.randn(1 << 20, device="cuda:0") for _ in range(3))
+    out = torch.empty_like(x)
+    p.stencil_stream_probe(x, None, None, out, x.numel() * 4)
     torch.cuda.synchronize()
-    assert torch.equal(x, y)
+    assert torch.equal(out, x)
+    p.stencil_stream_probe(x, y, z, out, x.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(out, (x + y) + z)
 
 
 @pytest.mark.slow
