@@ -143,6 +143,13 @@ void stencil_destroy(stencil_ctx *ctx);
  * device arrays of the grid's shape; they may be the same array. */
 stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void *stream);
 
+/* stencil_step with the output in its own buffer: reads u_cur = u^{it} and
+ * u_prev = u^{it-1}, writes u^{it+1} (sources included) to u_next. u_next may
+ * be u_prev (the in-place form) but must not otherwise overlap u_prev, and
+ * must not overlap u_cur or kappa (EALIAS). Same traffic as the in-place form. */
+stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
+                               void *u_next, int64_t it, const stencil_src *src, void *stream);
+
 /* One leapfrog step n = it: reads u_cur = u^{it} and u_prev_next = u^{it-1},
  * overwrites u_prev_next with u^{it+1}, then injects the sources (src may
  * be NULL). Requires it < src->nt when src is given (EINVAL). u_cur and
@@ -150,6 +157,40 @@ stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void 
  * u_prev_next. Pointers must be 16-byte aligned when the tile uses vw = 4. */
 stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur,
                             void *u_prev_next, int64_t it, const stencil_src *src, void *stream);
+
+/* kappa(p) = dt^2 / (h^2 m(p)) from squared slowness m = 1/v^2 (the model
+ * parameter of the gradient below), formed in FP64 and rounded once. */
+stencil_status stencil_kappa_slowness2(stencil_ctx *ctx, const void *m, void *kappa, void *stream);
+
+/* Receiver samples out[j] = u[idx[j]] for j < n (FP32; 0 for an index outside
+ * the grid). idx and out are device arrays of n entries. */
+stencil_status stencil_sample(stencil_ctx *ctx, const void *u, const int64_t *idx, int32_t n, void *out,
+                              void *stream);
+
+/* One step of the discrete adjoint of stencil_step, run backward in time.
+ * For the misfit J = 1/2 sum_k sum_r (u^k(r) - d^k(r))^2 the Lagrange
+ * multipliers obey lambda^k = 2 lambda^{k+1} - lambda^{k+2} + L(kappa lambda^{k+1}) + r^k
+ * (L symmetric); the library carries mu = kappa * lambda, whose recurrence
+ * mu^k = 2 mu^{k+1} - mu^{k+2} + kappa L mu^{k+1} + kappa r^k is the forward
+ * step with the residuals injected at the receivers. So: lam_cur = mu^{k+1},
+ * lam_prev_next = mu^{k+2} on entry and mu^k on exit, resid = receivers with
+ * residual rows (row `it` is injected; it = k-1 for traces recorded as row
+ * k-1 = u^k), same rules as stencil_step.
+ * If grad != NULL (FP64, [nz][ny][nx]) it also accumulates the gradient with
+ * respect to squared slowness m = 1/v^2:
+ *   grad += -(h^2/dt^2) * mu^k * (u_next - 2 u_cur + u_prev)
+ * with u_next = u^k, u_cur = u^{k-1}, u_prev = u^{k-2} (FP32 fields); summed
+ * over k = N..1 this is dJ/dm. grad must not overlap any other field
+ * (EALIAS). */
+stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const void *lam_cur, void *lam_prev_next,
+                                    int64_t it, const stencil_src *resid, const void *u_next, const void *u_cur,
+                                    const void *u_prev, double *grad, void *stream);
+
+/* resid[i] = traces[i] - observed[i] (FP32, i < count; resid may be NULL) and
+ * *misfit = 1/2 sum resid^2 accumulated in FP64 in a fixed order (device
+ * double). All pointers are device memory. */
+stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
+                              void *stream);
 
 /* The paper's two-phase blocksize search (Sections 3.2-3.3) on the
  * production shape: the selection phase times every candidate for n_iter
@@ -196,11 +237,12 @@ stencil_status stencil_select(const double *t, int32_t n_nodes, int32_t n_cores,
  * Writes at most cap values and returns the count (or EINVAL). */
 int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap);
 
-/* Bandwidth reference: out[i] = a[i] (+ b[i]) (+ c[i]) over nbytes of FP32
- * (a multiple of 16; 16-byte aligned device pointers; b may be NULL, c may be
- * NULL, c non-NULL needs b). With b = c = NULL it is a plain copy; with all
- * three it has the sweep's traffic mix of three reads per write. Enqueued on
- * `stream`. */
+/* Streaming reference: out[i] = a[i] (+ b[i]) (+ c[i]) over nbytes of FP32
+ * (a multiple of 4; 4-byte aligned device pointers; 16-byte vectors when the
+ * size and every pointer allow; b may be NULL, c may be NULL, c non-NULL
+ * needs b). With b = c = NULL it is a plain copy (used for wavefield
+ * checkpoints); with all three it has the sweep's traffic mix of three reads
+ * per write (the bandwidth reference). Enqueued on `stream`. */
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
                                     void *stream);
 

@@ -85,6 +85,12 @@ _sig = {
     "stencil_destroy": (None, [_vp]),
     "stencil_kappa": (_i32, [_vp, _vp, _vp, _vp]),
     "stencil_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
+    "stencil_step_to": (_i32, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
+    "stencil_kappa_slowness2": (_i32, [_vp, _vp, _vp, _vp]),
+    "stencil_sample": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
+    "stencil_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp, _vp, _vp, _vp,
+                                    _vp]),
+    "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "stencil_tune": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(StencilTuneOpts),
                             ctypes.POINTER(StencilTuneReport), _vp]),
     "stencil_get_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
@@ -181,6 +187,37 @@ def stencil_step(ctx, kappa, u_cur, u_prev_next, it=0, src: StencilSrc | None = 
                              ctypes.byref(src) if src is not None else None, _stream(stream)), ctx)
 
 
+def stencil_step_to(ctx, kappa, u_cur, u_prev, u_next, it=0, src: StencilSrc | None = None, stream=None):
+    _check(_lib.stencil_step_to(ctx, _ptr(kappa), _ptr(u_cur), _ptr(u_prev), _ptr(u_next), int(it),
+                                ctypes.byref(src) if src is not None else None, _stream(stream)), ctx)
+
+
+def stencil_kappa_slowness2(ctx, m, kappa, stream=None):
+    _check(_lib.stencil_kappa_slowness2(ctx, _ptr(m), _ptr(kappa), _stream(stream)), ctx)
+
+
+def stencil_sample(ctx, u, idx, out, stream=None):
+    """out[j] = u[idx[j]]; idx int64 and out float32 device tensors of one length."""
+    if out.numel() < idx.numel():
+        raise ValueError("out holds fewer entries than idx")
+    _check(_lib.stencil_sample(ctx, _ptr(u), _ptr(idx), int(idx.numel()), _ptr(out), _stream(stream)), ctx)
+
+
+def stencil_adjoint_step(ctx, kappa, lam_cur, lam_prev_next, it, resid: StencilSrc | None, u_next=None, u_cur=None,
+                         u_prev=None, grad=None, stream=None):
+    _check(_lib.stencil_adjoint_step(ctx, _ptr(kappa), _ptr(lam_cur), _ptr(lam_prev_next), int(it),
+                                     ctypes.byref(resid) if resid is not None else None, _ptr(u_next), _ptr(u_cur),
+                                     _ptr(u_prev), _ptr(grad), _stream(stream)), ctx)
+
+
+def stencil_misfit(traces, observed, resid, misfit, stream=None):
+    """resid = traces - observed; misfit (float64 device scalar) = 1/2 sum resid^2."""
+    if observed.numel() != traces.numel() or (resid is not None and resid.numel() != traces.numel()):
+        raise ValueError("traces, observed and resid must hold the same number of samples")
+    _check(_lib.stencil_misfit(_ptr(traces), _ptr(observed), int(traces.numel()), _ptr(resid), _ptr(misfit),
+                               _stream(stream)))
+
+
 def stencil_tune(ctx, kappa, scratch_a, scratch_b, policy="worst", n_iter=0, n_rep=0, warmup=0, parts=0,
                  include_plain=False, cache_path=None, table_cap=0, stream=None):
     """Run the blocksize search. Returns (report dict, table [n_rep][nC] or None,
@@ -275,19 +312,22 @@ class Propagator:
     with u^{n+1}."""
 
     def __init__(self, v, h: float, dt: float, radius: int = 4, vmax: float | None = None,
-                 tile: StencilTile | None = None):
+                 tile: StencilTile | None = None, slowness2: bool = False):
         import torch
         if v.dtype != torch.float32 or not v.is_cuda or v.dim() != 3 or not v.is_contiguous():
-            raise ValueError("v must be a contiguous float32 CUDA tensor [nz, ny, nx]")
+            raise ValueError("the model must be a contiguous float32 CUDA tensor [nz, ny, nx]")
         self.shape = tuple(v.shape)
         nz, ny, nx = self.shape
         if vmax is None:
-            vmax = float(v.max().item())
+            vmax = float(v.max().item()) if not slowness2 else float(v.min().item()) ** -0.5
         self.h, self.dt, self.radius = float(h), float(dt), int(radius)
         self.device = v.device
         self.ctx = stencil_init(nx, ny, nz, h, dt, vmax, radius, v.device.index or 0, tile)
         self.kappa = torch.empty_like(v)
-        stencil_kappa(self.ctx, v, self.kappa)
+        if slowness2:
+            stencil_kappa_slowness2(self.ctx, v, self.kappa)
+        else:
+            stencil_kappa(self.ctx, v, self.kappa)
 
     def __del__(self, _destroy=_lib.stencil_destroy):
         ctx = getattr(self, "ctx", None)

@@ -243,6 +243,13 @@ bool overlaps(const void *a, const void *b, int64_t bytes)
     return x < y + (uintptr_t)bytes && y < x + (uintptr_t)bytes;
 }
 
+// [a, a + la) and [b, b + lb) share a byte.
+bool overlaps2(const void *a, int64_t la, const void *b, int64_t lb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + (uintptr_t)lb && y < x + (uintptr_t)la;
+}
+
 // Makes ctx->d.device current for the lifetime of the guard.
 struct DeviceGuard {
     int prev = -1;
@@ -266,13 +273,14 @@ stencil_status hip_fail(stencil_ctx *ctx, hipError_t e, const char *what)
 
 // Enqueue one step with a given (already checked) tile.
 hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const float *kappa, const float *ucur,
-                        float *uprev, int64_t it, const stencil_src *src, hipStream_t s)
+                        const float *uprev, float *unext, int64_t it, const stencil_src *src, hipStream_t s)
 {
     const stencil_desc &d = ctx->d;
     SweepArgs a = {};
     a.kappa = kappa;
     a.ucur = ucur;
     a.uprev = uprev;
+    a.unext = unext;
     a.nx = (int)d.nx;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
@@ -296,7 +304,7 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
         e = p1310::launch_zmarch(*v, a, s);
     }
     if (e != hipSuccess) return e;
-    if (nsrc > 1) e = p1310::launch_inject(uprev, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, s);
+    if (nsrc > 1) e = p1310::launch_inject(unext, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, s);
     return e;
 }
 
@@ -394,7 +402,7 @@ double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, fl
                  int steps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipError_t *err)
 {
     for (int i = 0; i < warm; ++i) {
-        hipError_t e = enqueue_step(ctx, t, kappa, a, b, 0, nullptr, s);
+        hipError_t e = enqueue_step(ctx, t, kappa, a, b, b, 0, nullptr, s);
         if (e != hipSuccess) {
             *err = e;
             return std::numeric_limits<double>::infinity();
@@ -403,7 +411,7 @@ double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, fl
     }
     hipEventRecord(e0, s);
     for (int i = 0; i < steps; ++i) {
-        hipError_t e = enqueue_step(ctx, t, kappa, a, b, 0, nullptr, s);
+        hipError_t e = enqueue_step(ctx, t, kappa, a, b, b, 0, nullptr, s);
         if (e != hipSuccess) {
             *err = e;
             hipEventRecord(e1, s);
@@ -549,16 +557,18 @@ stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void 
     return STENCIL_OK;
 }
 
-stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur, void *u_prev_next, int64_t it,
-                            const stencil_src *src, void *stream)
+stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
+                               void *u_next, int64_t it, const stencil_src *src, void *stream)
 {
     if (!ctx) return STENCIL_EINVAL;
-    if (!kappa || !u_cur || !u_prev_next) return fail(ctx, STENCIL_EINVAL, "null field pointer");
+    if (!kappa || !u_cur || !u_prev || !u_next) return fail(ctx, STENCIL_EINVAL, "null field pointer");
     const int64_t bytes = npoints(ctx) * 4;
-    if (overlaps(u_cur, u_prev_next, bytes)) return fail(ctx, STENCIL_EALIAS, "u_cur overlaps u_prev_next");
-    if (overlaps(kappa, u_prev_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps u_prev_next");
+    if (overlaps(u_cur, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "u_cur overlaps the output");
+    if (overlaps(kappa, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps the output");
+    if (u_prev != u_next && overlaps(u_prev, u_next, bytes))
+        return fail(ctx, STENCIL_EALIAS, "u_prev partially overlaps the output");
     if (ctx->tile.vw == 4 &&
-        (((uintptr_t)kappa | (uintptr_t)u_cur | (uintptr_t)u_prev_next) & 15u))
+        (((uintptr_t)kappa | (uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next) & 15u))
         return fail(ctx, STENCIL_EINVAL, "fields must be 16-byte aligned for vw = 4");
     if (src && src->n != 0) {
         if (src->n < 0 || !src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
@@ -566,10 +576,16 @@ stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_c
     }
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = enqueue_step(ctx, ctx->tile, (const float *)kappa, (const float *)u_cur, (float *)u_prev_next, it,
-                                (src && src->n) ? src : nullptr, (hipStream_t)stream);
+    hipError_t e = enqueue_step(ctx, ctx->tile, (const float *)kappa, (const float *)u_cur, (const float *)u_prev,
+                                (float *)u_next, it, (src && src->n) ? src : nullptr, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "sweep launch");
     return STENCIL_OK;
+}
+
+stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur, void *u_prev_next, int64_t it,
+                            const stencil_src *src, void *stream)
+{
+    return stencil_step_to(ctx, kappa, u_cur, u_prev_next, u_prev_next, it, src, stream);
 }
 
 stencil_status stencil_select(const double *t, int32_t n_nodes, int32_t n_cores, int32_t n_cand, int32_t policy,
@@ -754,11 +770,75 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     return STENCIL_OK;
 }
 
+stencil_status stencil_kappa_slowness2(stencil_ctx *ctx, const void *m, void *kappa, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!m || !kappa) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = p1310::launch_kappa_m((const float *)m, (float *)kappa, npoints(ctx), ctx->d.dt, ctx->d.h,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "kappa launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_sample(stencil_ctx *ctx, const void *u, const int64_t *idx, int32_t n, void *out,
+                              void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (n < 0) return fail(ctx, STENCIL_EINVAL, "negative receiver count");
+    if (n == 0) return STENCIL_OK;
+    if (!u || !idx || !out) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = p1310::launch_sample((const float *)u, npoints(ctx), idx, n, (float *)out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sample launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const void *lam_cur, void *lam_prev_next,
+                                    int64_t it, const stencil_src *resid, const void *u_next, const void *u_cur,
+                                    const void *u_prev, double *grad, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (grad && (!u_next || !u_cur || !u_prev))
+        return fail(ctx, STENCIL_EINVAL, "gradient accumulation needs u_next, u_cur and u_prev");
+    if (grad) {
+        const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+        const void *fields[] = {kappa, lam_cur, lam_prev_next, u_next, u_cur, u_prev};
+        for (const void *f : fields)
+            if (overlaps2(grad, gb, f, fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
+        if (overlaps(lam_prev_next, u_next, fb) || overlaps(lam_prev_next, u_cur, fb) ||
+            overlaps(lam_prev_next, u_prev, fb))
+            return fail(ctx, STENCIL_EALIAS, "lam_prev_next overlaps a forward wavefield");
+    }
+    // The adjoint variable is mu = kappa * lambda; its recurrence is the
+    // forward step with the residuals injected at the receivers.
+    stencil_status st = stencil_step(ctx, kappa, lam_cur, lam_prev_next, it, resid, stream);
+    if (st != STENCIL_OK || !grad) return st;
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
+    hipError_t e = p1310::launch_grad(grad, (const float *)lam_prev_next, (const float *)u_next, (const float *)u_cur,
+                                      (const float *)u_prev, npoints(ctx), scale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
+                              void *stream)
+{
+    if (!traces || !observed || !misfit || count < 0) return STENCIL_EINVAL;
+    hipError_t e = p1310::launch_misfit((const float *)traces, (const float *)observed, count, (float *)resid, misfit,
+                                        (hipStream_t)stream);
+    return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
+}
+
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
                                     void *stream)
 {
-    if (!a || !out || (c && !b) || nbytes <= 0 || nbytes % 16 ||
-        (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)out) & 15u))
+    if (!a || !out || (c && !b) || nbytes <= 0 || nbytes % 4 ||
+        (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)out) & 3u))
         return STENCIL_EINVAL;
     hipError_t e = p1310::launch_stream(a, b, c, out, nbytes, (hipStream_t)stream);
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;

@@ -14,7 +14,8 @@ constexpr int kMaxRadius = 5;
 struct SweepArgs {
     const float *kappa;      // [nz][ny][nx]
     const float *ucur;       // u^n
-    float *uprev;            // u^{n-1} on entry, u^{n+1} on exit
+    const float *uprev;      // u^{n-1}
+    float *unext;            // u^{n+1} (may be uprev: in-place update)
     int nx, ny, nz;
     int dz;                  // planes per workgroup (z-march)
     int gx, gy, gz;          // tiles along x, y and z-chunks
@@ -44,6 +45,12 @@ hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipSt
 hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
                          const float *amp, int nsrc, int64_t it, hipStream_t s);
 hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, double h, hipStream_t s);
+hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, double h, hipStream_t s);
+hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s);
+hipError_t launch_grad(double *g, const float *mu, const float *un, const float *uc, const float *up, int64_t n,
+                       double scale, hipStream_t s);
+hipError_t launch_misfit(const float *tr, const float *obs, int64_t count, float *resid, double *misfit,
+                         hipStream_t s);
 hipError_t launch_stream(const void *a, const void *b, const void *c, void *out, int64_t nbytes, hipStream_t s);
 
 }  // namespace p1310

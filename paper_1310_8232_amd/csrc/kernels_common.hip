@@ -43,17 +43,103 @@ __global__ void __launch_bounds__(256) kappa_kernel(const float *v, float *kappa
     }
 }
 
-// Several point sources, added one after another in index order (so that
-// repeated indices accumulate deterministically).
-__global__ void __launch_bounds__(64) inject_kernel(float *u, const float *kappa, int64_t n_points,
-                                                    const int64_t *idx, const float *amp, int nsrc, int64_t it)
+// kappa = dt^2 / (h^2 m) from squared slowness m = 1/v^2, in FP64, rounded once.
+__global__ void __launch_bounds__(256) kappa_m_kernel(const float *m, float *kappa, int64_t n, double dt, double h)
 {
-    if (threadIdx.x != 0) return;
-    for (int j = 0; j < nsrc; ++j) {
-        const int64_t p = idx[j];
-        if (p < 0 || p >= n_points) continue;
-        u[p] = __builtin_fmaf(kappa[p], amp[it * nsrc + j], u[p]);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const double num = dt * dt / (h * h);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        kappa[i] = (float)(num / (double)m[i]);
+}
+
+// Several point sources, one thread per source. Repeated indices are added
+// by the thread of their first occurrence, in index order, so the result is
+// the same as adding the sources one after another.
+__global__ void __launch_bounds__(256) inject_kernel(float *u, const float *kappa, int64_t n_points,
+                                                     const int64_t *idx, const float *amp, int nsrc, int64_t it)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsrc) return;
+    const int64_t p = idx[j];
+    if (p < 0 || p >= n_points) return;
+    for (int k = 0; k < j; ++k)
+        if (idx[k] == p) return;  // an earlier source owns this point
+    const float kp = kappa[p];
+    float v = u[p];
+    for (int k = j; k < nsrc; ++k)
+        if (idx[k] == p) v = __builtin_fmaf(kp, amp[it * nsrc + k], v);
+    u[p] = v;
+}
+
+// Receiver samples: out[j] = u[idx[j]] (0 for an index outside the grid).
+__global__ void __launch_bounds__(256) sample_kernel(const float *u, int64_t n_points, const int64_t *idx, int n,
+                                                     float *out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t p = idx[j];
+    out[j] = (p >= 0 && p < n_points) ? u[p] : 0.0f;
+}
+
+// Gradient accumulation (FP64): g += s * mu * (u^{k} - 2 u^{k-1} + u^{k-2}).
+__global__ void __launch_bounds__(256) grad_kernel(double *g, const float *mu, const float *un, const float *uc,
+                                                   const float *up, int64_t n, double s)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double d2 = ((double)un[i] - 2.0 * (double)uc[i]) + (double)up[i];
+        g[i] += s * ((double)mu[i] * d2);
     }
+}
+
+// Same, four points per thread from 16-byte FP32 vectors and two 16-byte FP64
+// pairs, each workgroup streaming one contiguous chunk (n4 = points / 4).
+constexpr int64_t kGradChunk = 1024;  // float4 groups per workgroup
+
+__global__ void __launch_bounds__(256) grad_kernel_vec4(double *g, const float *mu, const float *un, const float *uc,
+                                                        const float *up, int64_t n4, double s)
+{
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const int64_t beg = (int64_t)blockIdx.x * kGradChunk;
+    const int64_t end = (beg + kGradChunk < n4) ? beg + kGradChunk : n4;
+    for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
+        const f4v m = __builtin_nontemporal_load((const f4v *)mu + i);
+        const f4v a = __builtin_nontemporal_load((const f4v *)un + i);
+        const f4v b = __builtin_nontemporal_load((const f4v *)uc + i);
+        const f4v c = __builtin_nontemporal_load((const f4v *)up + i);
+        d2v *gp = (d2v *)g + 2 * i;
+        d2v g0 = gp[0], g1 = gp[1];
+        g0.x += s * ((double)m.x * (((double)a.x - 2.0 * (double)b.x) + (double)c.x));
+        g0.y += s * ((double)m.y * (((double)a.y - 2.0 * (double)b.y) + (double)c.y));
+        g1.x += s * ((double)m.z * (((double)a.z - 2.0 * (double)b.z) + (double)c.z));
+        g1.y += s * ((double)m.w * (((double)a.w - 2.0 * (double)b.w) + (double)c.w));
+        gp[0] = g0;
+        gp[1] = g1;
+    }
+}
+
+// resid = traces - observed (FP32), misfit = 1/2 sum resid^2 accumulated in
+// FP64 by one workgroup in a fixed order (deterministic).
+constexpr int kMisfitThreads = 1024;
+
+__global__ void __launch_bounds__(kMisfitThreads) misfit_kernel(const float *tr, const float *obs, int64_t count,
+                                                                float *resid, double *misfit)
+{
+    __shared__ double part[kMisfitThreads];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += kMisfitThreads) {
+        const float r = tr[i] - obs[i];
+        if (resid) resid[i] = r;
+        acc += (double)r * (double)r;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kMisfitThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *misfit = 0.5 * part[0];
 }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -91,6 +177,20 @@ __global__ void __launch_bounds__(256) stream_kernel(const f4 *a, const f4 *b, c
     }
 }
 
+// Same for any size and 4-byte alignment, one float per thread per step.
+template <int NIN>
+__global__ void __launch_bounds__(256) stream_kernel_scalar(const float *a, const float *b, const float *c, float *out,
+                                                            int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float v = __builtin_nontemporal_load(&a[i]);
+        if (NIN > 1) v += __builtin_nontemporal_load(&b[i]);
+        if (NIN > 2) v += __builtin_nontemporal_load(&c[i]);
+        __builtin_nontemporal_store(v, &out[i]);
+    }
+}
+
 }  // namespace
 
 int zmarch_variant_count() { return registry().n; }
@@ -121,7 +221,46 @@ hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipSt
 hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
                          const float *amp, int nsrc, int64_t it, hipStream_t s)
 {
-    hipLaunchKernelGGL(inject_kernel, dim3(1), dim3(64), 0, s, u, kappa, n_points, idx, amp, nsrc, it);
+    hipLaunchKernelGGL(inject_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, u, kappa, n_points, idx, amp, nsrc,
+                       it);
+    return hipGetLastError();
+}
+
+hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, double h, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kappa_m_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, kappa, n, dt, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, s, u, n_points, idx, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(double *g, const float *mu, const float *un, const float *uc, const float *up, int64_t n,
+                       double scale, hipStream_t s)
+{
+    if (n % 4 == 0 && !(((uintptr_t)g | (uintptr_t)mu | (uintptr_t)un | (uintptr_t)uc | (uintptr_t)up) & 15u)) {
+        const int64_t n4 = n / 4;
+        const int64_t blocks = (n4 + kGradChunk - 1) / kGradChunk;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(grad_kernel_vec4, dim3((unsigned)blocks), dim3(256), 0, s, g, mu, un, uc, up, n4, scale);
+        return hipGetLastError();
+    }
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(grad_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, mu, un, uc, up, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit(const float *tr, const float *obs, int64_t count, float *resid, double *misfit, hipStream_t s)
+{
+    hipLaunchKernelGGL(misfit_kernel, dim3(1), dim3(kMisfitThreads), 0, s, tr, obs, count, resid, misfit);
     return hipGetLastError();
 }
 
@@ -136,6 +275,23 @@ hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, doub
 
 hipError_t launch_stream(const void *a, const void *b, const void *c, void *out, int64_t nbytes, hipStream_t s)
 {
+    if ((nbytes % 16) || (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)out) & 15u)) {
+        const int64_t n = nbytes / 4;
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        if (blocks < 1) blocks = 1;
+        const float *sa = (const float *)a, *sb = (const float *)b, *sc = (const float *)c;
+        if (c)
+            hipLaunchKernelGGL(stream_kernel_scalar<3>, dim3((unsigned)blocks), dim3(256), 0, s, sa, sb, sc,
+                               (float *)out, n);
+        else if (b)
+            hipLaunchKernelGGL(stream_kernel_scalar<2>, dim3((unsigned)blocks), dim3(256), 0, s, sa, sb, sc,
+                               (float *)out, n);
+        else
+            hipLaunchKernelGGL(stream_kernel_scalar<1>, dim3((unsigned)blocks), dim3(256), 0, s, sa, sb, sc,
+                               (float *)out, n);
+        return hipGetLastError();
+    }
     const int64_t n4 = nbytes / 16;
     const int64_t blocks = (n4 + kStreamChunk - 1) / kStreamChunk;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;

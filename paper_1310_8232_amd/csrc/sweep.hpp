@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
     const uint32_t win = (uint32_t)(zhi - zlo) * pbytes;
     const rsrc_t rc = make_rsrc(a.ucur + zlo * plane, win);
     const rsrc_t rp = make_rsrc(a.uprev + zlo * plane, win);
+    const rsrc_t rn = make_rsrc(a.unext + zlo * plane, win);
     const rsrc_t rk = make_rsrc(a.kappa + zlo * plane, win);
 
     // ---- this thread's points and halo items (same offsets every plane) ----
@@ -327,7 +328,7 @@ __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
                             out[jj].a[e] = __builtin_fmaf(kp[jj].a[e], s_amp, out[jj].a[e]);
             }
 #pragma unroll
-            for (int jj = 0; jj < RY; ++jj) bstore<VW, kNT>(out[jj], rp, coff[jj], so);
+            for (int jj = 0; jj < RY; ++jj) bstore<VW, kNT>(out[jj], rn, coff[jj], so);
         }
     }
 }
@@ -363,7 +364,7 @@ __global__ void __launch_bounds__(1024) plain_kernel(SweepArgs a)
     const float k = a.kappa[p];
     float o = __builtin_fmaf(k, acc, __builtin_fmaf(2.0f, u0, -a.uprev[p]));
     if (a.nsrc == 1 && a.src_idx[0] == p) o = __builtin_fmaf(k, a.src_amp[a.it], o);
-    a.uprev[p] = o;
+    a.unext[p] = o;
 }
 
 }  // namespace p1310

@@ -161,6 +161,6 @@ def test_step_argument_errors_before_launch():
 
 def test_stream_probe_validation():
     with pytest.raises(p.StencilError):
-        p.stencil_stream_probe(1 << 40, None, None, (1 << 40) + 4096, 100, stream=0)
+        p.stencil_stream_probe(1 << 40, None, None, (1 << 40) + 4096, 102, stream=0)
     with pytest.raises(p.StencilError):
         p.stencil_stream_probe(1 << 40, None, (1 << 40) + 8192, (1 << 40) + 4096, 4096, stream=0)

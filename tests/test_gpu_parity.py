@@ -236,6 +236,11 @@ def test_stream_probe():
     p.stencil_stream_probe(x, y, z, out, x.numel() * 4)
     torch.cuda.synchronize()
     assert torch.equal(out, (x + y) + z)
+    # Odd size and 4-byte offsets take the scalar path.
+    out.zero_()
+    p.stencil_stream_probe(x[1:], None, None, out[1:], (x.numel() - 3) * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(out[1:-2], x[1:-2]) and out[0] == 0 and out[-2:].eq(0).all()
 
 
 @pytest.mark.slow

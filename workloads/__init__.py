@@ -97,3 +97,43 @@ def config_layered(nx: int = 512, ny: int = 512, nz: int = 512, nt: int = 1000, 
     return dict(name=f"layered {nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, h=h, dt=dt, vmax=vmax,
                 v=v, radius=radius, nt=nt, src_idx=np.array([centre_index(nx, ny, nz)], np.int64),
                 amp=ricker(nt, dt))
+
+
+def blob_factor(nx: int, ny: int, nz: int, seed: int, amplitude: float = -0.05, width: float | None = None):
+    """1 + amplitude * exp(-r^2 / (2 w^2)) around a seeded centre in the middle
+    half of each axis (w = min(n)/8 by default), FP64 [nz, ny, nx]."""
+    rng = np.random.default_rng(seed)
+    cz, cy, cx = (rng.uniform(0.25, 0.75) * (n - 1) for n in (nz, ny, nx))
+    w = width if width is not None else min(nx, ny, nz) / 8.0
+    z = np.arange(nz)[:, None, None] - cz
+    y = np.arange(ny)[None, :, None] - cy
+    x = np.arange(nx)[None, None, :] - cx
+    return 1.0 + amplitude * np.exp(-(x * x + y * y + z * z) / (2.0 * w * w))
+
+
+def receiver_line(nx: int, ny: int, nz: int, radius: int = 4) -> np.ndarray:
+    """Linear indices of every x in [R, nx-R) at y = ny//2, z = min(2R, nz-1)."""
+    z = min(2 * radius, nz - 1)
+    xs = np.arange(radius, max(nx - radius, radius + 1))
+    xs = xs[xs < nx]
+    return ((z * ny + ny // 2) * nx + xs).astype(np.int64)
+
+
+def config_gradient(nx: int = 256, ny: int = 256, nz: int = 256, nt: int = 500, seed: int = SEED + 2,
+                    radius: int = 4, courant: float = 0.4, f0: float = 15.0, blob: float = -0.05,
+                    blob_width: float | None = None):
+    """Gradient workload: true layered model (seed), current model with a
+    seeded Gaussian blob of `blob` relative velocity (-5%), source
+    (z = 2R, ny//2, nx//2), Ricker of peak frequency f0, receiver line at
+    z = 2R; squared slowness m = 1/v^2 (FP32)."""
+    h = 10.0
+    v_true = layered_model(nx, ny, nz, seed)
+    v_cur = (v_true.astype(np.float64) * blob_factor(nx, ny, nz, seed + 1, blob, blob_width)).astype(np.float32)
+    dt, vmax = dt_for_courant(v_true, h, courant)
+    zs = min(2 * radius, nz - 1)
+    src = np.array([(zs * ny + ny // 2) * nx + nx // 2], np.int64)
+    m_true = (1.0 / (v_true.astype(np.float64) ** 2)).astype(np.float32)
+    m_cur = (1.0 / (v_cur.astype(np.float64) ** 2)).astype(np.float32)
+    return dict(name=f"gradient {nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, h=h, dt=dt, vmax=vmax, radius=radius,
+                nt=nt, v_true=v_true, v_cur=v_cur, m_true=m_true, m_cur=m_cur, src_idx=src,
+                amp=ricker(nt, dt, f0), rec_idx=receiver_line(nx, ny, nz, radius))
