@@ -53,6 +53,7 @@ typedef enum {
 } stencil_status;
 
 typedef struct stencil_ctx stencil_ctx;  /* opaque */
+typedef struct stencil_batch stencil_batch;  /* opaque */
 
 typedef enum { STENCIL_F32 = 0 } stencil_storage;
 
@@ -192,6 +193,39 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
 stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
                               void *stream);
 
+/* One shot of a batch: its context (grid, weights, current tile), kappa and
+ * two wavefield buffers (device, borrowed), and its sources (src.n = 0 for
+ * none; idx/amp device pointers as in stencil_src). */
+typedef struct {
+    stencil_ctx *ctx;
+    const void *kappa;
+    void *u_a;
+    void *u_b;
+    stencil_src src;
+} stencil_shot;
+
+/* Several independent grids (shots, each with its own size and tuned tile)
+ * advanced together. Shots whose tiles use the same compiled kernel are swept
+ * by one launch per step (the launch grid concatenates their workgroups; each
+ * keeps its own march depth); plain-tile shots get a launch of their own.
+ * Copies each context's current tile; allocates one small device table
+ * (hipMalloc, here only). Buffers alternate: at step `it` with
+ * (it - it0) even, u_a holds u^{it}, u_b holds u^{it-1} and receives u^{it+1};
+ * with (it - it0) odd the roles swap. Rejects a null or aliased shot (EINVAL /
+ * EALIAS) and mixed devices. */
+stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out);
+
+/* One step of every shot of the batch on `stream`; capture-safe (no
+ * allocation, no synchronisation). EINVAL if it < it0 or it reaches the
+ * shortest source length. */
+stencil_status stencil_batch_step(stencil_batch *b, int64_t it, void *stream);
+
+/* Kernel launches one batch step issues. */
+int32_t stencil_batch_launches(const stencil_batch *b);
+
+/* Release a batch (NULL is ignored). Does not free the shots' buffers. */
+void stencil_batch_destroy(stencil_batch *b);
+
 /* The paper's two-phase blocksize search (Sections 3.2-3.3) on the
  * production shape: the selection phase times every candidate for n_iter
  * steps, n_rep times in the same fixed order, and reduces the table with
@@ -249,7 +283,9 @@ stencil_status stencil_stream_probe(const void *a, const void *b, const void *c,
 /* Message for a status code (static storage). */
 const char *stencil_strerror(stencil_status s);
 
-/* Last error message recorded on the context ("" if none). */
+/* Last error message recorded on the context ("" if none); with ctx = NULL,
+ * the calling thread's last message from calls that take no context
+ * (batches, misfit, streaming reference). */
 const char *stencil_last_error(const stencil_ctx *ctx);
 
 #ifdef __cplusplus

@@ -64,6 +64,11 @@ class StencilSrc(ctypes.Structure):
                 ("nt", ctypes.c_int64)]
 
 
+class StencilShot(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("kappa", ctypes.c_void_p), ("u_a", ctypes.c_void_p),
+                ("u_b", ctypes.c_void_p), ("src", StencilSrc)]
+
+
 class StencilTuneOpts(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("n_rep", ctypes.c_int32),
                 ("warmup", ctypes.c_int32), ("parts", ctypes.c_int32), ("include_plain", ctypes.c_int32),
@@ -91,6 +96,10 @@ _sig = {
     "stencil_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp, _vp, _vp, _vp,
                                     _vp]),
     "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
+    "stencil_batch_create": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
+    "stencil_batch_step": (_i32, [_vp, _i64, _vp]),
+    "stencil_batch_launches": (_i32, [_vp]),
+    "stencil_batch_destroy": (None, [_vp]),
     "stencil_tune": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(StencilTuneOpts),
                             ctypes.POINTER(StencilTuneReport), _vp]),
     "stencil_get_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
@@ -122,10 +131,9 @@ class StencilError(RuntimeError):
 def _check(status: int, ctx=None):
     if status != OK:
         msg = stencil_strerror(status)
-        if ctx:
-            extra = _lib.stencil_last_error(ctx)
-            if extra:
-                msg = f"{msg}: {extra.decode()}"
+        extra = _lib.stencil_last_error(ctx)
+        if extra:
+            msg = f"{msg}: {extra.decode()}"
         raise StencilError(status, msg)
 
 
@@ -216,6 +224,30 @@ def stencil_misfit(traces, observed, resid, misfit, stream=None):
         raise ValueError("traces, observed and resid must hold the same number of samples")
     _check(_lib.stencil_misfit(_ptr(traces), _ptr(observed), int(traces.numel()), _ptr(resid), _ptr(misfit),
                                _stream(stream)))
+
+
+def stencil_batch_create(shots, it0: int = 0):
+    """shots: list of (ctx, kappa, u_a, u_b, StencilSrc or None). Returns a handle."""
+    arr = (StencilShot * len(shots))()
+    for i, (ctx, kap, ua, ub, src) in enumerate(shots):
+        arr[i] = StencilShot(ctx, _ptr(kap), _ptr(ua), _ptr(ub), src if src is not None else StencilSrc())
+    out = _vp()
+    _check(_lib.stencil_batch_create(arr, len(shots), int(it0), ctypes.byref(out)))
+    return out.value
+
+
+def stencil_batch_step(batch, it: int, stream=None):
+    _check(_lib.stencil_batch_step(batch, int(it), _stream(stream)))
+
+
+def stencil_batch_launches(batch) -> int:
+    n = _lib.stencil_batch_launches(batch)
+    _check(min(n, 0))
+    return n
+
+
+def stencil_batch_destroy(batch):
+    _lib.stencil_batch_destroy(batch)
 
 
 def stencil_tune(ctx, kappa, scratch_a, scratch_b, policy="worst", n_iter=0, n_rep=0, warmup=0, parts=0,
@@ -371,3 +403,46 @@ class Propagator:
         if scratch_b is None:
             scratch_b = torch.zeros_like(self.kappa)
         return stencil_tune(self.ctx, self.kappa, scratch_a, scratch_b, **opts)
+
+
+class Batch:
+    """Several Propagators (shots) stepped together by stencil_batch_step.
+
+    ``shots``: list of (Propagator, StencilSrc or None). Each shot gets two
+    zeroed wavefield buffers; after an even number of steps from it0 buffer
+    ``u_a`` holds the newest wavefield, after an odd number ``u_b``."""
+
+    def __init__(self, shots, it0: int = 0):
+        import torch
+        self.props = [pr for pr, _ in shots]
+        self.srcs = [src for _, src in shots]
+        self.u_a = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
+        self.u_b = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
+        self.it0 = int(it0)
+        self.handle = stencil_batch_create(
+            [(pr.ctx, pr.kappa, a, b, src) for pr, a, b, src in zip(self.props, self.u_a, self.u_b, self.srcs)],
+            it0)
+
+    def __del__(self, _destroy=_lib.stencil_batch_destroy):
+        h = getattr(self, "handle", None)
+        if h:
+            _destroy(h)
+            self.handle = None
+
+    @property
+    def launches_per_step(self) -> int:
+        return stencil_batch_launches(self.handle)
+
+    def step(self, it: int, stream=None):
+        stencil_batch_step(self.handle, it, stream)
+
+    def run(self, nt: int, it0: int | None = None, stream=None):
+        start = self.it0 if it0 is None else it0
+        for it in range(start, start + nt):
+            stencil_batch_step(self.handle, it, stream)
+
+    def current(self, steps_done: int):
+        """(u^n, u^{n-1}) tensors of every shot after `steps_done` steps from it0."""
+        if steps_done % 2 == 0:
+            return list(zip(self.u_a, self.u_b))
+        return list(zip(self.u_b, self.u_a))

@@ -27,6 +27,31 @@ struct stencil_ctx {
     std::string err;
 };
 
+struct stencil_batch {
+    struct Shot {
+        stencil_ctx *ctx;
+        const float *kappa;
+        float *u_a, *u_b;
+        stencil_src src;
+        stencil_tile tile;
+    };
+    struct Group {
+        const p1310::ZVariant *v;
+        int xcd;
+        int nshots;
+        int blocks;
+        p1310::SweepArgs *tab[2];  // device: step parity 0 / 1
+        int *begin;                // device: first workgroup of each shot
+    };
+    std::vector<Shot> shots;
+    std::vector<Group> groups;
+    std::vector<int> solo;  // shots launched on their own (plain tiles)
+    int64_t it0 = 0;
+    int64_t nt_min = 0;     // smallest source length (steps must stay below it)
+    void *dmem = nullptr;
+    int device = 0;
+};
+
 namespace {
 
 constexpr int kXcds = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
@@ -101,11 +126,17 @@ double cfl_limit_of(int R)
     return 2.0 / std::sqrt(3.0 * std::fabs(rat_to_double(s)));
 }
 
+// Last error of calls made without a context (batches, misfit, probe), per thread.
+thread_local std::string g_err;
+
 stencil_status fail(stencil_ctx *ctx, stencil_status st, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
+    else g_err = msg;
     return st;
 }
+
+size_t round256(size_t n) { return (n + 255) / 256 * 256; }
 
 int64_t npoints(const stencil_ctx *c) { return c->d.nx * c->d.ny * c->d.nz; }
 
@@ -449,7 +480,7 @@ const char *stencil_strerror(stencil_status s)
     return "unknown status";
 }
 
-const char *stencil_last_error(const stencil_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char *stencil_last_error(const stencil_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
 double stencil_cfl_limit(int32_t radius) { return radius_ok(radius) ? cfl_limit_of(radius) : -1.0; }
 
@@ -832,6 +863,184 @@ stencil_status stencil_misfit(const void *traces, const void *observed, int64_t 
     hipError_t e = p1310::launch_misfit((const float *)traces, (const float *)observed, count, (float *)resid, misfit,
                                         (hipStream_t)stream);
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
+}
+
+stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out)
+{
+    if (!shots || !out || n < 1 || n > 4096) return STENCIL_EINVAL;
+    stencil_batch *bt = new (std::nothrow) stencil_batch;
+    if (!bt) return STENCIL_ENOMEM;
+    bt->it0 = it0;
+    bt->nt_min = std::numeric_limits<int64_t>::max();
+    bt->device = shots[0].ctx ? shots[0].ctx->d.device : 0;
+    for (int i = 0; i < n; ++i) {
+        const stencil_shot &sh = shots[i];
+        if (!sh.ctx || !sh.kappa || !sh.u_a || !sh.u_b || sh.ctx->d.device != bt->device) {
+            delete bt;
+            return STENCIL_EINVAL;
+        }
+        const int64_t bytes = npoints(sh.ctx) * 4;
+        if (overlaps(sh.u_a, sh.u_b, bytes) || overlaps(sh.kappa, sh.u_a, bytes) || overlaps(sh.kappa, sh.u_b, bytes)) {
+            delete bt;
+            return STENCIL_EALIAS;
+        }
+        if (sh.ctx->tile.vw == 4 && (((uintptr_t)sh.kappa | (uintptr_t)sh.u_a | (uintptr_t)sh.u_b) & 15u)) {
+            delete bt;
+            return STENCIL_EINVAL;
+        }
+        if (sh.src.n < 0 || (sh.src.n > 0 && (!sh.src.idx || !sh.src.amp || sh.src.nt < 1))) {
+            delete bt;
+            return STENCIL_EINVAL;
+        }
+        if (sh.src.n > 0) bt->nt_min = std::min(bt->nt_min, sh.src.nt);
+        bt->shots.push_back({sh.ctx, (const float *)sh.kappa, (float *)sh.u_a, (float *)sh.u_b, sh.src, sh.ctx->tile});
+    }
+    // Group the z-march shots by compiled kernel (tile shape) and XCD order.
+    for (int i = 0; i < n; ++i) {
+        const stencil_tile &t = bt->shots[i].tile;
+        if (t.kind != STENCIL_TILE_ZMARCH) {
+            bt->solo.push_back(i);
+            continue;
+        }
+        const ZVariant *v = find_variant(bt->shots[i].ctx->R, t);
+        bool placed = false;
+        for (auto &g : bt->groups)
+            if (g.v == v && g.xcd == t.xcd) {
+                ++g.nshots;
+                placed = true;
+            }
+        if (!placed) bt->groups.push_back({v, t.xcd, 1, 0, {nullptr, nullptr}, nullptr});
+    }
+    // Host tables, then one device allocation for every group.
+    std::vector<std::vector<SweepArgs>> tabs[2];
+    std::vector<std::vector<int>> begins;
+    size_t total = 0;
+    for (auto &g : bt->groups) {
+        std::vector<SweepArgs> t0, t1;
+        std::vector<int> beg;
+        int64_t blocks = 0;
+        for (int i = 0; i < n; ++i) {
+            const auto &sh = bt->shots[i];
+            if (sh.tile.kind != STENCIL_TILE_ZMARCH || find_variant(sh.ctx->R, sh.tile) != g.v || sh.tile.xcd != g.xcd)
+                continue;
+            const stencil_desc &d = sh.ctx->d;
+            SweepArgs a = {};
+            a.kappa = sh.kappa;
+            a.nx = (int)d.nx;
+            a.ny = (int)d.ny;
+            a.nz = (int)d.nz;
+            for (int m = 0; m <= sh.ctx->R; ++m) a.c[m] = sh.ctx->cf[m];
+            a.dz = sh.tile.dz;
+            a.gx = (int)((d.nx + (int64_t)sh.tile.bx * sh.tile.vw - 1) / ((int64_t)sh.tile.bx * sh.tile.vw));
+            a.gy = (int)((d.ny + (int64_t)sh.tile.by * sh.tile.ry - 1) / ((int64_t)sh.tile.by * sh.tile.ry));
+            a.gz = (int)((d.nz + sh.tile.dz - 1) / sh.tile.dz);
+            a.xcd = 0;  // the batch applies the XCD order over the whole launch
+            a.nsrc = sh.src.n == 1 ? 1 : 0;
+            a.src_idx = sh.src.n == 1 ? sh.src.idx : nullptr;
+            a.src_amp = sh.src.n == 1 ? sh.src.amp : nullptr;
+            beg.push_back((int)blocks);
+            blocks += (int64_t)a.gx * a.gy * a.gz;
+            SweepArgs e = a, o = a;
+            e.ucur = sh.u_a;
+            e.uprev = sh.u_b;
+            e.unext = sh.u_b;
+            o.ucur = sh.u_b;
+            o.uprev = sh.u_a;
+            o.unext = sh.u_a;
+            t0.push_back(e);
+            t1.push_back(o);
+        }
+        if (blocks > 0x7fffffff) {
+            delete bt;
+            return STENCIL_EUNSUPPORTED;
+        }
+        g.blocks = (int)blocks;
+        tabs[0].push_back(t0);
+        tabs[1].push_back(t1);
+        begins.push_back(beg);
+        total += 2 * round256(t0.size() * sizeof(SweepArgs)) + round256(beg.size() * sizeof(int));
+    }
+    if (!bt->groups.empty()) {
+        DeviceGuard guard(bt->device);
+        hipError_t he = guard.status != hipSuccess ? guard.status : hipMalloc(&bt->dmem, total);
+        if (he != hipSuccess) {
+            delete bt;
+            return hip_fail(nullptr, he, "batch table allocation");
+        }
+        char *p = (char *)bt->dmem;
+        for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
+            auto &g = bt->groups[gi];
+            for (int par = 0; par < 2; ++par) {
+                g.tab[par] = (SweepArgs *)p;
+                size_t sz = tabs[par][gi].size() * sizeof(SweepArgs);
+                hipError_t he = hipMemcpy(p, tabs[par][gi].data(), sz, hipMemcpyHostToDevice);
+                if (he != hipSuccess) {
+                    hipFree(bt->dmem);
+                    delete bt;
+                    return hip_fail(nullptr, he, "batch table upload");
+                }
+                p += round256(sz);
+            }
+            g.begin = (int *)p;
+            size_t sz = begins[gi].size() * sizeof(int);
+            hipError_t he = hipMemcpy(p, begins[gi].data(), sz, hipMemcpyHostToDevice);
+            if (he != hipSuccess) {
+                hipFree(bt->dmem);
+                delete bt;
+                return hip_fail(nullptr, he, "batch table upload");
+            }
+            p += round256(sz);
+        }
+    }
+    *out = bt;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_batch_step(stencil_batch *bt, int64_t it, void *stream)
+{
+    if (!bt) return STENCIL_EINVAL;
+    if (it < bt->it0 || it >= bt->nt_min) return STENCIL_EINVAL;
+    const int par = (int)((it - bt->it0) & 1);
+    DeviceGuard guard(bt->device);
+    if (guard.status != hipSuccess) return STENCIL_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    for (auto &g : bt->groups) {
+        hipError_t e = p1310::launch_zmarch_batch(*g.v, g.tab[par], g.begin, g.nshots, g.blocks, g.xcd, it, s);
+        if (e != hipSuccess) return STENCIL_EDEVICE;
+    }
+    for (size_t i = 0; i < bt->shots.size(); ++i) {
+        const auto &sh = bt->shots[i];
+        const float *uc = par ? sh.u_b : sh.u_a;
+        float *up = par ? sh.u_a : sh.u_b;
+        const bool solo = sh.tile.kind != STENCIL_TILE_ZMARCH;
+        if (solo) {
+            hipError_t e = enqueue_step(sh.ctx, sh.tile, sh.kappa, uc, up, up, it, sh.src.n ? &sh.src : nullptr, s);
+            if (e != hipSuccess) return STENCIL_EDEVICE;
+        } else if (sh.src.n > 1) {
+            hipError_t e = p1310::launch_inject(up, sh.kappa, npoints(sh.ctx), sh.src.idx, sh.src.amp, sh.src.n, it, s);
+            if (e != hipSuccess) return STENCIL_EDEVICE;
+        }
+    }
+    return STENCIL_OK;
+}
+
+int32_t stencil_batch_launches(const stencil_batch *bt)
+{
+    if (!bt) return STENCIL_EINVAL;
+    int32_t k = (int32_t)bt->groups.size() + (int32_t)bt->solo.size();
+    for (const auto &sh : bt->shots)
+        if (sh.tile.kind == STENCIL_TILE_ZMARCH && sh.src.n > 1) ++k;
+    return k;
+}
+
+void stencil_batch_destroy(stencil_batch *bt)
+{
+    if (!bt) return;
+    if (bt->dmem) {
+        DeviceGuard guard(bt->device);
+        (void)hipFree(bt->dmem);
+    }
+    delete bt;
 }
 
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,

@@ -31,6 +31,7 @@ struct SweepArgs {
 struct ZVariant {
     int R, bx, by, ry, vw, pf;
     void (*kernel)(SweepArgs);
+    void (*batch_kernel)(const SweepArgs *, const int *, int, int, int64_t);
     int threads;
     int lds_bytes;
 };
@@ -41,6 +42,8 @@ const ZVariant *zmarch_variant(int i);
 
 // Launchers (kernels.hip). All enqueue on `s` and return the launch status.
 hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s);
+hipError_t launch_zmarch_batch(const ZVariant &v, const SweepArgs *shots, const int *wg_begin, int nshots,
+                               int total_blocks, int xcd, int64_t it, hipStream_t s);
 hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
 hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
                          const float *amp, int nsrc, int64_t it, hipStream_t s);

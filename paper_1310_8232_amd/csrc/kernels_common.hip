@@ -208,6 +208,13 @@ hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_zmarch_batch(const ZVariant &v, const SweepArgs *shots, const int *wg_begin, int nshots,
+                               int total_blocks, int xcd, int64_t it, hipStream_t s)
+{
+    hipLaunchKernelGGL(v.batch_kernel, dim3(total_blocks), dim3(v.threads), 0, s, shots, wg_begin, nshots, xcd, it);
+    return hipGetLastError();
+}
+
 hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipStream_t s)
 {
     switch (R) {

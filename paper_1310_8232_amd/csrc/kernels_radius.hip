@@ -13,7 +13,8 @@ namespace p1310 {
 
 // (BX, BY, RY, VW, PF) of every z-march instantiation.
 #define ZV(BX, BY, RY, VW, PF)                                                                  \
-    {RADIUS, BX, BY, RY, VW, PF, zmarch_kernel<RADIUS, BX, BY, RY, VW, PF>, BX * BY,            \
+    {RADIUS, BX, BY, RY, VW, PF, zmarch_kernel<RADIUS, BX, BY, RY, VW, PF>,                     \
+     zmarch_batch_kernel<RADIUS, BX, BY, RY, VW, PF>, BX * BY,                                  \
      (int)(2 * (((BY * RY + 2 * RADIUS) * (BX * VW + 2 * ((VW == 1) ? RADIUS : ((RADIUS + VW - 1) / VW) * VW))) + VW) * 4)},
 
 static const ZVariant kTable[] = {

@@ -102,7 +102,7 @@ __device__ __forceinline__ int xcd_order(int b, int nblk, int nxcd)
 // compile-time constant (no register moves for the shift).
 // ---------------------------------------------------------------------------
 template <int R, int BX, int BY, int RY, int VW, int PF>
-__global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
+__device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
 {
     constexpr int NT = BX * BY;
     constexpr int TX = BX * VW, TY = BY * RY;
@@ -120,9 +120,7 @@ __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
 
     __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
 
-    // ---- tile of this workgroup --------------------------------------------
-    int b = blockIdx.x;
-    if (a.xcd > 1) b = xcd_order(b, gridDim.x, a.xcd);
+    // ---- tile of this workgroup (b = tile id within the grid) --------------
     const int tile_x = b % a.gx;
     const int t2 = b / a.gx;
     const int tile_y = t2 % a.gy;
@@ -331,6 +329,30 @@ __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
             for (int jj = 0; jj < RY; ++jj) bstore<VW, kNT>(out[jj], rn, coff[jj], so);
         }
     }
+}
+
+template <int R, int BX, int BY, int RY, int VW, int PF>
+__global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
+{
+    int b = blockIdx.x;
+    if (a.xcd > 1) b = xcd_order(b, gridDim.x, a.xcd);
+    zmarch_body<R, BX, BY, RY, VW, PF>(a, b);
+}
+
+// Several grids (shots) in one launch: the launch grid concatenates every
+// shot's workgroups; wg_begin[s] is the first workgroup of shot s. Each shot
+// keeps its own sizes, march depth, fields and source; `it` is the step.
+template <int R, int BX, int BY, int RY, int VW, int PF>
+__global__ void __launch_bounds__(BX * BY) zmarch_batch_kernel(const SweepArgs *shots, const int *wg_begin,
+                                                               int nshots, int xcd, int64_t it)
+{
+    int b = blockIdx.x;
+    if (xcd > 1) b = xcd_order(b, gridDim.x, xcd);
+    int s = 0;
+    while (s + 1 < nshots && wg_begin[s + 1] <= b) ++s;
+    SweepArgs a = shots[s];
+    a.it = it;
+    zmarch_body<R, BX, BY, RY, VW, PF>(a, b - wg_begin[s]);
 }
 
 // ---------------------------------------------------------------------------

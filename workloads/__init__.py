@@ -137,3 +137,28 @@ def config_gradient(nx: int = 256, ny: int = 256, nz: int = 256, nt: int = 500, 
     return dict(name=f"gradient {nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, h=h, dt=dt, vmax=vmax, radius=radius,
                 nt=nt, v_true=v_true, v_cur=v_cur, m_true=m_true, m_cur=m_cur, src_idx=src,
                 amp=ricker(nt, dt, f0), rec_idx=receiver_line(nx, ny, nz, radius))
+
+
+def batch_shapes(seed: int = SEED + 1, n: int = 16):
+    """Shot grid sizes (nx, ny, nz): 384x192x128, 96^3, 256^3, then dims drawn
+    from multiples of 32 in [96, 384], redrawn until the volume lies in
+    [96^3, 256^3]."""
+    rng = np.random.default_rng(seed)
+    out = [(384, 192, 128), (96, 96, 96), (256, 256, 256)]
+    choices = np.arange(96, 385, 32)
+    while len(out) < n:
+        d = tuple(int(x) for x in rng.choice(choices, size=3))
+        if 96 ** 3 <= d[0] * d[1] * d[2] <= 256 ** 3:
+            out.append(d)
+    return out[:n]
+
+
+def config_batch(n: int = 16, nt: int = 500, seed: int = SEED + 1, shapes=None):
+    """Uneven shots: each with its own layered model (seed SEED + 100 + i),
+    h = 10 m, Courant 0.4 on its own max velocity, centred 15 Hz Ricker."""
+    shapes = shapes or batch_shapes(seed, n)
+    shots = []
+    for i, (nx, ny, nz) in enumerate(shapes):
+        c = config_layered(nx, ny, nz, nt=nt, seed=SEED + 100 + i)
+        shots.append(c)
+    return shots
