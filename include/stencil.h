@@ -220,6 +220,18 @@ stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_
  * shortest source length. */
 stencil_status stencil_batch_step(stencil_batch *b, int64_t it, void *stream);
 
+/* The blocksize search of stencil_tune run on a whole batch: every candidate
+ * tile (those of the first shot's search that every shot can run) is applied
+ * to all shots at once and timed as a batch step, so the choice is made under
+ * the contention of the production run (the situation that motivates the
+ * same-order evaluation of Section 3.3). The shots' u_a/u_b are used as
+ * scratch and overwritten; sources are not injected while timing. Sets every
+ * shot's context tile to the winner and fills *report
+ * (default_time_ms = the shots' own tiles). opts may be NULL; cache_path is
+ * ignored. Synchronises `stream`. */
+stencil_status stencil_batch_tune(const stencil_shot *shots, int32_t n, const stencil_tune_opts *opts,
+                                  stencil_tune_report *report, void *stream);
+
 /* Kernel launches one batch step issues. */
 int32_t stencil_batch_launches(const stencil_batch *b);
 

@@ -98,6 +98,8 @@ _sig = {
     "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "stencil_batch_create": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
     "stencil_batch_step": (_i32, [_vp, _i64, _vp]),
+    "stencil_batch_tune": (_i32, [ctypes.POINTER(StencilShot), _i32, ctypes.POINTER(StencilTuneOpts),
+                                  ctypes.POINTER(StencilTuneReport), _vp]),
     "stencil_batch_launches": (_i32, [_vp]),
     "stencil_batch_destroy": (None, [_vp]),
     "stencil_tune": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(StencilTuneOpts),
@@ -228,12 +230,30 @@ def stencil_misfit(traces, observed, resid, misfit, stream=None):
 
 def stencil_batch_create(shots, it0: int = 0):
     """shots: list of (ctx, kappa, u_a, u_b, StencilSrc or None). Returns a handle."""
+    out = _vp()
+    _check(_lib.stencil_batch_create(_shot_array(shots), len(shots), int(it0), ctypes.byref(out)))
+    return out.value
+
+
+def _shot_array(shots):
     arr = (StencilShot * len(shots))()
     for i, (ctx, kap, ua, ub, src) in enumerate(shots):
         arr[i] = StencilShot(ctx, _ptr(kap), _ptr(ua), _ptr(ub), src if src is not None else StencilSrc())
-    out = _vp()
-    _check(_lib.stencil_batch_create(arr, len(shots), int(it0), ctypes.byref(out)))
-    return out.value
+    return arr
+
+
+def stencil_batch_tune(shots, policy="worst", n_iter=0, n_rep=0, warmup=0, parts=0, include_plain=False,
+                       stream=None):
+    """Search one tile for a whole batch; shots as for stencil_batch_create.
+    Returns the report dict; every shot's context tile is set to the winner."""
+    pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
+    opts = StencilTuneOpts(pol, n_iter, n_rep, warmup, parts, int(bool(include_plain)), None, None, None, 0)
+    rep = StencilTuneReport()
+    _check(_lib.stencil_batch_tune(_shot_array(shots), len(shots), ctypes.byref(opts), ctypes.byref(rep),
+                                   _stream(stream)))
+    return {"tile": rep.tile.as_dict(), "min_time_ms": rep.min_time_ms, "actual_time_ms": rep.actual_time_ms,
+            "gap": rep.gap, "default_time_ms": rep.default_time_ms, "seconds": rep.seconds,
+            "n_candidates": rep.n_candidates}
 
 
 def stencil_batch_step(batch, it: int, stream=None):
@@ -412,16 +432,23 @@ class Batch:
     zeroed wavefield buffers; after an even number of steps from it0 buffer
     ``u_a`` holds the newest wavefield, after an odd number ``u_b``."""
 
-    def __init__(self, shots, it0: int = 0):
+    def __init__(self, shots, it0: int = 0, tune: dict | None = None):
         import torch
         self.props = [pr for pr, _ in shots]
         self.srcs = [src for _, src in shots]
         self.u_a = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
         self.u_b = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
         self.it0 = int(it0)
-        self.handle = stencil_batch_create(
-            [(pr.ctx, pr.kappa, a, b, src) for pr, a, b, src in zip(self.props, self.u_a, self.u_b, self.srcs)],
-            it0)
+        spec = [(pr.ctx, pr.kappa, a, b, src) for pr, a, b, src in zip(self.props, self.u_a, self.u_b, self.srcs)]
+        self.tune_report = None
+        if tune is not None:
+            # One tile for the whole batch, searched under batch contention;
+            # the buffers were scratch during the search and are cleared.
+            self.tune_report = stencil_batch_tune(spec, **tune)
+            for x, y in zip(self.u_a, self.u_b):
+                x.zero_()
+                y.zero_()
+        self.handle = stencil_batch_create(spec, it0)
 
     def __del__(self, _destroy=_lib.stencil_batch_destroy):
         h = getattr(self, "handle", None)

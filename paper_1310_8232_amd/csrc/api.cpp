@@ -865,7 +865,11 @@ stencil_status stencil_misfit(const void *traces, const void *observed, int64_t 
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
 }
 
-stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out)
+namespace {
+
+// Builds a batch; tiles[i] (when tiles != NULL) replaces shot i's context tile.
+stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_tile *tiles, int64_t it0,
+                           stencil_batch **out)
 {
     if (!shots || !out || n < 1 || n > 4096) return STENCIL_EINVAL;
     stencil_batch *bt = new (std::nothrow) stencil_batch;
@@ -893,7 +897,8 @@ stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_
             return STENCIL_EINVAL;
         }
         if (sh.src.n > 0) bt->nt_min = std::min(bt->nt_min, sh.src.nt);
-        bt->shots.push_back({sh.ctx, (const float *)sh.kappa, (float *)sh.u_a, (float *)sh.u_b, sh.src, sh.ctx->tile});
+        bt->shots.push_back({sh.ctx, (const float *)sh.kappa, (float *)sh.u_a, (float *)sh.u_b, sh.src,
+                             tiles ? tiles[i] : sh.ctx->tile});
     }
     // Group the z-march shots by compiled kernel (tile shape) and XCD order.
     for (int i = 0; i < n; ++i) {
@@ -996,6 +1001,13 @@ stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_
     return STENCIL_OK;
 }
 
+}  // namespace
+
+stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out)
+{
+    return build_batch(shots, n, nullptr, it0, out);
+}
+
 stencil_status stencil_batch_step(stencil_batch *bt, int64_t it, void *stream)
 {
     if (!bt) return STENCIL_EINVAL;
@@ -1041,6 +1053,106 @@ void stencil_batch_destroy(stencil_batch *bt)
         (void)hipFree(bt->dmem);
     }
     delete bt;
+}
+
+stencil_status stencil_batch_tune(const stencil_shot *shots, int32_t n, const stencil_tune_opts *opts,
+                                  stencil_tune_report *report, void *stream)
+{
+    if (!shots || n < 1 || n > 4096 || !report || !shots[0].ctx) return STENCIL_EINVAL;
+    stencil_tune_opts o = {};
+    if (opts) o = *opts;
+    if (o.policy < STENCIL_POLICY_WORST || o.policy > STENCIL_POLICY_OB || o.n_iter < 0 || o.n_rep < 0 ||
+        o.parts < 0 || o.parts == 1 || o.table_cap < 0)
+        return fail(nullptr, STENCIL_EINVAL, "bad tune options");
+    const int n_iter = o.n_iter ? o.n_iter : 10;
+    const int n_rep = o.n_rep ? o.n_rep : 3;
+    const int warm = o.warmup == 0 ? 2 : (o.warmup < 0 ? 0 : o.warmup);
+    *report = stencil_tune_report{};
+    const auto t_start = std::chrono::steady_clock::now();
+    // Timing copies of the shots without sources.
+    std::vector<stencil_shot> quiet(shots, shots + n);
+    for (auto &q : quiet) q.src = stencil_src{};
+    // Candidates: those of the first shot that every shot can run.
+    std::vector<stencil_tile> base = make_candidates(shots[0].ctx, o);
+    std::vector<std::vector<stencil_tile>> cands;  // per candidate: one tile per shot
+    std::vector<stencil_tile> cand_key;
+    for (const auto &t : base) {
+        std::vector<stencil_tile> per(n);
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i) {
+            std::string keep = shots[i].ctx->err;
+            ok = check_tile(shots[i].ctx, t, &per[i]) == STENCIL_OK;
+            shots[i].ctx->err = keep;
+        }
+        if (ok) {
+            cands.push_back(per);
+            cand_key.push_back(t);
+        }
+    }
+    const int nC = (int)cands.size();
+    if (nC == 0) return fail(nullptr, STENCIL_EUNSUPPORTED, "no tile fits every shot");
+    DeviceGuard g(shots[0].ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(nullptr, g.status, "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(nullptr, he, "hipEventCreate");
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(nullptr, he, "hipEventCreate");
+    }
+    auto time_batch = [&](const stencil_tile *tiles) -> double {
+        stencil_batch *bt = nullptr;
+        if (build_batch(quiet.data(), n, tiles, 0, &bt) != STENCIL_OK) return std::numeric_limits<double>::infinity();
+        double ms = std::numeric_limits<double>::infinity();
+        bool okk = true;
+        for (int i = 0; i < warm && okk; ++i) okk = stencil_batch_step(bt, i, s) == STENCIL_OK;
+        if (okk) {
+            hipEventRecord(e0, s);
+            for (int i = 0; i < n_iter && okk; ++i) okk = stencil_batch_step(bt, warm + i, s) == STENCIL_OK;
+            hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) == hipSuccess && okk) {
+                float f = 0;
+                hipEventElapsedTime(&f, e0, e1);
+                ms = f;
+            }
+        }
+        stencil_batch_destroy(bt);
+        return ms;
+    };
+    std::vector<double> table((size_t)n_rep * nC, std::numeric_limits<double>::infinity());
+    for (int r = 0; r < n_rep; ++r)
+        for (int c = 0; c < nC; ++c) table[(size_t)r * nC + c] = time_batch(cands[c].data());
+    bool any = false;
+    for (double v : table) any = any || std::isfinite(v);
+    if (!any) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        return fail(nullptr, STENCIL_EDEVICE, "every batch candidate failed");
+    }
+    int32_t best = 0;
+    double min_time = 0;
+    stencil_select(table.data(), 1, n_rep, nC, o.policy, &best, &min_time);
+    const double actual = time_batch(cands[best].data());
+    const double dtime = time_batch(nullptr);  // the shots' own tiles
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (int i = 0; i < n; ++i) shots[i].ctx->tile = cands[best][i];
+    report->tile = cand_key[best];
+    report->min_time_ms = min_time;
+    report->actual_time_ms = actual;
+    report->gap = (actual - min_time) / min_time;
+    report->default_time_ms = dtime;
+    report->n_candidates = nC;
+    report->from_cache = 0;
+    report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (o.table && o.table_cap > 0)
+        for (int r = 0; r < n_rep; ++r)
+            for (int c = 0; c < nC && c < o.table_cap; ++c) o.table[(size_t)r * o.table_cap + c] = table[(size_t)r * nC + c];
+    if (o.candidates)
+        for (int c = 0; c < nC && c < o.table_cap; ++c) o.candidates[c] = cand_key[c];
+    return STENCIL_OK;
 }
 
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,

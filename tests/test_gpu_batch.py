@@ -159,3 +159,26 @@ def test_batch_16_shots_bits_and_oracle():
     e1, e2 = oracle.rel_l2(x.cpu().numpy(), ref_n), oracle.rel_l2(y.cpu().numpy(), ref_nm1)
     log(f"  96^3 shot after 100 batch steps: rel_l2 {e1:.2e} / {e2:.2e}")
     assert e1 <= 1e-5 and e2 <= 1e-5
+
+
+def test_batch_tune_sets_one_tile_and_keeps_bits():
+    nt = 10
+    shots = [s for s in _shots(nt) if s["v"].shape[2] % 4 == 0]  # vector tiles for every shot
+    made = [_make(sh) for sh in shots]
+    batch = p.Batch([(pr, src) for pr, src, _ in made], tune=dict(n_iter=2, n_rep=2, parts=3))
+    rep = batch.tune_report
+    log(f"case: batch search over {rep['n_candidates']} candidates -> {rep['tile']} gap {rep['gap']:+.3f}")
+    assert rep["n_candidates"] > 0 and np.isfinite(rep["actual_time_ms"])
+    key = {k: rep["tile"][k] for k in ("kind", "bx", "by", "ry", "vw", "xcd", "pf")}
+    for pr, _, _ in made:
+        t = pr.tile.as_dict()
+        assert {k: t[k] for k in key} == key
+        assert t["dz"] == min(rep["tile"]["dz"], pr.shape[0])
+    assert batch.launches_per_step == 1 + sum(1 for s in shots if s["idx"] is not None and len(s["idx"]) > 1)
+    batch.run(nt)
+    torch.cuda.synchronize()
+    for i, ((pr, src, _), (x, y)) in enumerate(zip(made, batch.current(nt))):
+        a = torch.zeros(pr.shape, device="cuda:0")
+        b = torch.zeros(pr.shape, device="cuda:0")
+        a, b = pr.run(a, b, nt, src)
+        assert torch.equal(x, a) and torch.equal(y, b), f"shot {i}"
