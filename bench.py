@@ -276,6 +276,51 @@ def batch_bench(args) -> int:
     return 0
 
 
+def precision_bench(args) -> int:
+    """The same sweep with the wavefield stored as FP32, FP16 and BF16 (scaled),
+    FP32 arithmetic, on the 1024x1024x512 layered model: throughput per
+    storage type (each with its own tuned tile)."""
+    import torch
+
+    import paper_1310_8232_amd as p
+    import workloads
+
+    nx, ny, nz = 1024, 1024, 512
+    nt = args.steps
+    c = workloads.config_layered(nx, ny, nz, nt=nt + args.warmup, seed=workloads.SEED + 3)
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(c["v"]).to(dev)
+    idx = torch.tensor(c["src_idx"], dtype=torch.int64, device=dev)
+    amp = torch.from_numpy(c["amp"].reshape(-1, 1)).to(dev)
+    npts = nx * ny * nz
+    res = {}
+    for storage, nbytes in (("f32", 16), ("f16", 10), ("bf16", 10)):
+        prop = p.Propagator(v, c["h"], c["dt"], 4, vmax=c["vmax"], storage=storage,
+                            storage_scale=1.0 if storage == "f32" else 2.0 ** 12)
+        rep, _, _ = prop.tune(n_iter=args.tune_iter, n_rep=args.tune_rep, parts=args.tune_parts)
+        src = p.make_src(idx, amp)
+        a, b = prop.zeros(), prop.zeros()
+        a, b = prop.run(a, b, args.warmup, src)
+        ms, a, b = time_steps(prop, a, b, nt, args.warmup, src, torch.cuda.current_stream())
+        step = ms / nt
+        res[storage] = {"gpts": round(npts / (step * 1e-3) / 1e9, 2), "ms_per_step": round(step, 5),
+                        "bytes_per_update": nbytes,
+                        "hbm_gbs_algorithmic": round(nbytes * npts / (step * 1e-3) / 1e9, 1),
+                        "tile": prop.tile.as_dict(), "tune_s": round(rep["seconds"], 2)}
+        del prop, a, b
+        torch.cuda.empty_cache()
+    out = {"metric": "Gpoint-updates/s by wavefield storage type, 1024x1024x512 8th-order, FP32 arithmetic",
+           "value": res["f16"]["gpts"], "unit": "Gpt/s", "n_gpus": 1, "steps": nt, "warmup": args.warmup,
+           "ms_per_step": res["f16"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f16 storage, f32 compute", "data": "synthetic",
+           "config": {"workload": f"layered 1024x1024x512, R=4, {nt} steps, storage scale 2^12 for 16-bit",
+                      "by_storage": res,
+                      "speedup_f16_vs_f32": round(res["f16"]["gpts"] / res["f32"]["gpts"], 3),
+                      "speedup_bf16_vs_f32": round(res["bf16"]["gpts"] / res["f32"]["gpts"], 3)}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -291,7 +336,7 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "gradient", "batch"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision"), default="sweep",
                     help="sweep: the autotuned step (default); gradient: misfit + adjoint gradient; "
                          "batch: 16 uneven shots")
     ap.add_argument("--nt", type=int, default=0, help="time steps of the gradient workload (default 500)")
@@ -320,6 +365,8 @@ def main(argv=None):
         return gradient_bench(args)
     if args.workload == "batch":
         return batch_bench(args)
+    if args.workload == "precision":
+        return precision_bench(args)
     n = args.n
     nt = args.warmup + args.steps
     t0 = time.perf_counter()

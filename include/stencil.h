@@ -55,7 +55,10 @@ typedef enum {
 typedef struct stencil_ctx stencil_ctx;  /* opaque */
 typedef struct stencil_batch stencil_batch;  /* opaque */
 
-typedef enum { STENCIL_F32 = 0 } stencil_storage;
+/* Wavefield storage (kappa is always FP32; arithmetic is always FP32). The
+ * 16-bit types hold storage_scale * u, widened to FP32 on load and rounded to
+ * nearest even once per store; available for R = 4 and 5. */
+typedef enum { STENCIL_F32 = 0, STENCIL_F16 = 1, STENCIL_BF16 = 2 } stencil_storage;
 
 typedef enum {
     STENCIL_TILE_AUTO = 0,   /* the context's current tile (tuned, cached or built-in default) */
@@ -81,12 +84,14 @@ typedef struct {
 typedef struct {
     int64_t nx, ny, nz;   /* grid points, each >= 1 */
     int32_t radius;       /* R in {3, 4, 5}: order 2R in space (4 = 8th order, 25 points; 5 = the paper's 10th) */
-    int32_t storage;      /* stencil_storage: STENCIL_F32 */
+    int32_t storage;      /* stencil_storage */
     double h;             /* grid spacing (isotropic), > 0 */
     double dt;            /* time step, > 0 */
     double vmax;          /* largest velocity of the model, > 0, used for the stability check */
     int32_t device;       /* HIP device ordinal of the fields */
     stencil_tile tile;    /* kind 0 = tune cache entry if any, else the built-in default */
+    double storage_scale; /* wavefields are stored as storage_scale * u; a power of two (0 = 1).
+                             The scheme is linear, so only source amplitudes are multiplied by it. */
 } stencil_desc;
 
 /* Point sources (all device memory, borrowed): idx[n] linear indices,
@@ -144,6 +149,9 @@ void stencil_destroy(stencil_ctx *ctx);
  * device arrays of the grid's shape; they may be the same array. */
 stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void *stream);
 
+/* (Wavefield arguments of the stepping calls are in the context's storage
+ * type; with vw = 4 they must be aligned to 4 values, kappa to 16 bytes.) */
+
 /* stencil_step with the output in its own buffer: reads u_cur = u^{it} and
  * u_prev = u^{it-1}, writes u^{it+1} (sources included) to u_next. u_next may
  * be u_prev (the in-place form) but must not otherwise overlap u_prev, and
@@ -164,7 +172,8 @@ stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_c
 stencil_status stencil_kappa_slowness2(stencil_ctx *ctx, const void *m, void *kappa, void *stream);
 
 /* Receiver samples out[j] = u[idx[j]] for j < n (FP32; 0 for an index outside
- * the grid). idx and out are device arrays of n entries. */
+ * the grid). idx and out are device arrays of n entries. FP32 storage only
+ * (EUNSUPPORTED otherwise); so is stencil_adjoint_step. */
 stencil_status stencil_sample(stencil_ctx *ctx, const void *u, const int64_t *idx, int32_t n, void *out,
                               void *stream);
 
@@ -255,10 +264,16 @@ stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out);
  * context's grid (EUNSUPPORTED) without changing the current one. */
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
-/* Legal ZMARCH tiles for a radius, with vw = 4 (vec4 != 0) or 1, dz = 0.
- * Writes at most cap entries to out (out may be NULL) and returns the total
- * count, or a negative stencil_status. */
-int32_t stencil_list_tiles(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap);
+/* Compiled ZMARCH tiles for a radius and storage type, with vw = 4
+ * (vec4 != 0) or 1, dz = 0. Writes at most cap entries to out (out may be
+ * NULL) and returns the total count, or a negative stencil_status. */
+int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stencil_tile *out, int32_t cap);
+
+/* Between FP32 wavefields and the context's storage: to_storage != 0 writes
+ * dst = round(src * storage_scale) (nearest even) in the storage type;
+ * to_storage = 0 writes FP32 dst = src / storage_scale. Whole grid, device
+ * memory, no overlap (EALIAS). */
+stencil_status stencil_convert(stencil_ctx *ctx, const void *src, void *dst, int32_t to_storage, void *stream);
 
 /* FP32 weights the kernels use: out[0] = 3*c_0, out[m] = c_m (m = 1..R).
  * Returns R+1, or EINVAL for an unsupported radius. */

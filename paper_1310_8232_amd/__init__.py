@@ -33,7 +33,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- status codes and enums (include/stencil.h) ----------------------------
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EUNSUPPORTED, EALIAS = 0, -1, -2, -3, -4, -5, -6
-F32 = 0
+F32, F16, BF16 = 0, 1, 2
+STORAGES = {"f32": F32, "f16": F16, "bf16": BF16}
 TILE_AUTO, TILE_PLAIN, TILE_ZMARCH = 0, 1, 2
 POLICY_WORST, POLICY_MIN, POLICY_AVG, POLICY_OB = 0, 1, 2, 3
 POLICIES = {"worst": POLICY_WORST, "mwmb": POLICY_WORST, "min": POLICY_MIN, "mmmb": POLICY_MIN,
@@ -56,7 +57,7 @@ class StencilDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("radius", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("h", ctypes.c_double), ("dt", ctypes.c_double), ("vmax", ctypes.c_double),
-                ("device", ctypes.c_int32), ("tile", StencilTile)]
+                ("device", ctypes.c_int32), ("tile", StencilTile), ("storage_scale", ctypes.c_double)]
 
 
 class StencilSrc(ctypes.Structure):
@@ -106,7 +107,8 @@ _sig = {
                             ctypes.POINTER(StencilTuneReport), _vp]),
     "stencil_get_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
     "stencil_set_tile": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
-    "stencil_list_tiles": (_i32, [_i32, _i32, ctypes.POINTER(StencilTile), _i32]),
+    "stencil_list_tiles": (_i32, [_i32, _i32, _i32, ctypes.POINTER(StencilTile), _i32]),
+    "stencil_convert": (_i32, [_vp, _vp, _vp, _i32, _vp]),
     "stencil_coefficients": (_i32, [_i32, ctypes.POINTER(ctypes.c_float)]),
     "stencil_cfl_limit": (ctypes.c_double, [_i32]),
     "stencil_select": (_i32, [ctypes.POINTER(ctypes.c_double), _i32, _i32, _i32, _i32,
@@ -169,9 +171,12 @@ def make_tile(kind=TILE_ZMARCH, bx=0, by=0, ry=1, dz=0, vw=0, xcd=1, pf=0) -> St
     return StencilTile(kind, bx, by, ry, dz, vw, xcd, pf)
 
 
-def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile | None = None):
+def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile | None = None, storage=F32,
+                 storage_scale: float = 1.0):
     """Create a context; returns an opaque handle (int)."""
-    d = StencilDesc(nx, ny, nz, radius, F32, h, dt, vmax, device, tile if tile is not None else StencilTile())
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    d = StencilDesc(nx, ny, nz, radius, st, h, dt, vmax, device, tile if tile is not None else StencilTile(),
+                    storage_scale)
     out = _vp()
     _check(_lib.stencil_init(ctypes.byref(d), ctypes.byref(out)))
     return out.value
@@ -307,12 +312,17 @@ def stencil_set_tile(ctx, tile: StencilTile):
     _check(_lib.stencil_set_tile(ctx, ctypes.byref(tile)), ctx)
 
 
-def stencil_list_tiles(radius: int, vec4: bool = True):
-    n = _lib.stencil_list_tiles(radius, int(vec4), None, 0)
+def stencil_list_tiles(radius: int, vec4: bool = True, storage=F32):
+    st = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    n = _lib.stencil_list_tiles(radius, int(vec4), st, None, 0)
     _check(min(n, 0))
     arr = (StencilTile * max(n, 1))()
-    _lib.stencil_list_tiles(radius, int(vec4), arr, n)
+    _lib.stencil_list_tiles(radius, int(vec4), st, arr, n)
     return [arr[i] for i in range(n)]
+
+
+def stencil_convert(ctx, src, dst, to_storage: bool, stream=None):
+    _check(_lib.stencil_convert(ctx, _ptr(src), _ptr(dst), int(bool(to_storage)), _stream(stream)), ctx)
 
 
 def stencil_coefficients(radius: int):
@@ -364,7 +374,8 @@ class Propagator:
     with u^{n+1}."""
 
     def __init__(self, v, h: float, dt: float, radius: int = 4, vmax: float | None = None,
-                 tile: StencilTile | None = None, slowness2: bool = False):
+                 tile: StencilTile | None = None, slowness2: bool = False, storage="f32",
+                 storage_scale: float = 1.0):
         import torch
         if v.dtype != torch.float32 or not v.is_cuda or v.dim() != 3 or not v.is_contiguous():
             raise ValueError("the model must be a contiguous float32 CUDA tensor [nz, ny, nx]")
@@ -374,7 +385,11 @@ class Propagator:
             vmax = float(v.max().item()) if not slowness2 else float(v.min().item()) ** -0.5
         self.h, self.dt, self.radius = float(h), float(dt), int(radius)
         self.device = v.device
-        self.ctx = stencil_init(nx, ny, nz, h, dt, vmax, radius, v.device.index or 0, tile)
+        self.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
+        self.storage_scale = float(storage_scale)
+        self.dtype = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[self.storage]
+        self.ctx = stencil_init(nx, ny, nz, h, dt, vmax, radius, v.device.index or 0, tile, self.storage,
+                                storage_scale)
         self.kappa = torch.empty_like(v)
         if slowness2:
             stencil_kappa_slowness2(self.ctx, v, self.kappa)
@@ -388,9 +403,27 @@ class Propagator:
             self.ctx = None
 
     def _check_field(self, t):
+        if t.dtype != self.dtype or not t.is_cuda or tuple(t.shape) != self.shape or not t.is_contiguous():
+            raise ValueError(f"fields must be contiguous {self.dtype} CUDA tensors of shape {self.shape}")
+
+    def zeros(self):
+        """A zero wavefield in the storage type."""
         import torch
-        if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != self.shape or not t.is_contiguous():
-            raise ValueError(f"fields must be contiguous float32 CUDA tensors of shape {self.shape}")
+        return torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+
+    def to_storage(self, u32):
+        """storage_scale * u rounded to the storage type (device kernel)."""
+        import torch
+        out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        stencil_convert(self.ctx, u32.contiguous(), out, True)
+        return out
+
+    def to_f32(self, u):
+        """FP32 u from a stored wavefield (device kernel)."""
+        import torch
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        stencil_convert(self.ctx, u, out, False)
+        return out
 
     @property
     def tile(self) -> StencilTile:
@@ -417,11 +450,10 @@ class Propagator:
         return a, b
 
     def tune(self, scratch_a=None, scratch_b=None, **opts):
-        import torch
         if scratch_a is None:
-            scratch_a = torch.zeros_like(self.kappa)
+            scratch_a = self.zeros()
         if scratch_b is None:
-            scratch_b = torch.zeros_like(self.kappa)
+            scratch_b = self.zeros()
         return stencil_tune(self.ctx, self.kappa, scratch_a, scratch_b, **opts)
 
 
@@ -436,8 +468,8 @@ class Batch:
         import torch
         self.props = [pr for pr, _ in shots]
         self.srcs = [src for _, src in shots]
-        self.u_a = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
-        self.u_b = [torch.zeros(pr.shape, device=pr.device) for pr in self.props]
+        self.u_a = [pr.zeros() for pr in self.props]
+        self.u_b = [pr.zeros() for pr in self.props]
         self.it0 = int(it0)
         spec = [(pr.ctx, pr.kappa, a, b, src) for pr, a, b, src in zip(self.props, self.u_a, self.u_b, self.srcs)]
         self.tune_report = None

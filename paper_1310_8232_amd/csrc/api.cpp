@@ -22,6 +22,9 @@ using p1310::ZVariant;
 struct stencil_ctx {
     stencil_desc d;
     int R = 4;
+    int st = p1310::kF32;  // wavefield storage
+    int es = 4;            // bytes per wavefield value
+    float scale = 1.0f;    // storage scale (power of two)
     float cf[p1310::kMaxRadius + 1] = {};  // 3*c_0, c_1..c_R in FP32
     stencil_tile tile = {};
     std::string err;
@@ -31,7 +34,7 @@ struct stencil_batch {
     struct Shot {
         stencil_ctx *ctx;
         const float *kappa;
-        float *u_a, *u_b;
+        void *u_a, *u_b;
         stencil_src src;
         stencil_tile tile;
     };
@@ -142,11 +145,12 @@ int64_t npoints(const stencil_ctx *c) { return c->d.nx * c->d.ny * c->d.nz; }
 
 bool vec4_ok(const stencil_ctx *c) { return c->d.nx % 4 == 0; }
 
-const ZVariant *find_variant(int R, const stencil_tile &t)
+const ZVariant *find_variant(const stencil_ctx *ctx, const stencil_tile &t)
 {
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R == R && v->bx == t.bx && v->by == t.by && v->ry == t.ry && v->vw == t.vw && v->pf == t.pf)
+        if (v->R == ctx->R && v->st == ctx->st && v->bx == t.bx && v->by == t.by && v->ry == t.ry && v->vw == t.vw &&
+            v->pf == t.pf)
             return v;
     }
     return nullptr;
@@ -175,7 +179,7 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
     if (t.vw == 4 && !vec4_ok(ctx))
         return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
-    if (!find_variant(ctx->R, t))
+    if (!find_variant(ctx, t))
         return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
     if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
     if (t.dz > d.nz) t.dz = (int32_t)d.nz;
@@ -215,7 +219,7 @@ stencil_tile default_tile(const stencil_ctx *ctx)
     } else {
         t.bx = 64;
         t.by = 4;
-        t.ry = 2;
+        t.ry = ctx->st == p1310::kF32 ? 2 : 1;
         t.vw = 1;
     }
     t.dz = 64;
@@ -303,8 +307,8 @@ stencil_status hip_fail(stencil_ctx *ctx, hipError_t e, const char *what)
 }
 
 // Enqueue one step with a given (already checked) tile.
-hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const float *kappa, const float *ucur,
-                        const float *uprev, float *unext, int64_t it, const stencil_src *src, hipStream_t s)
+hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const float *kappa, const void *ucur,
+                        const void *uprev, void *unext, int64_t it, const stencil_src *src, hipStream_t s)
 {
     const stencil_desc &d = ctx->d;
     SweepArgs a = {};
@@ -316,6 +320,7 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
     for (int m = 0; m <= ctx->R; ++m) a.c[m] = ctx->cf[m];
+    a.scale = ctx->scale;
     const int nsrc = src ? src->n : 0;
     a.nsrc = (nsrc == 1) ? 1 : 0;
     a.src_idx = nsrc == 1 ? src->idx : nullptr;
@@ -323,9 +328,9 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
     a.it = it;
     hipError_t e;
     if (t.kind == STENCIL_TILE_PLAIN) {
-        e = p1310::launch_plain(ctx->R, t.bx, t.by, t.dz, a, s);
+        e = p1310::launch_plain(ctx->R, ctx->st, t.bx, t.by, t.dz, a, s);
     } else {
-        const ZVariant *v = find_variant(ctx->R, t);
+        const ZVariant *v = find_variant(ctx, t);
         if (!v) return hipErrorInvalidValue;
         a.dz = t.dz;
         a.gx = (int)((d.nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw));
@@ -335,7 +340,8 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
         e = p1310::launch_zmarch(*v, a, s);
     }
     if (e != hipSuccess) return e;
-    if (nsrc > 1) e = p1310::launch_inject(unext, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, s);
+    if (nsrc > 1)
+        e = p1310::launch_inject(ctx->st, unext, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, ctx->scale, s);
     return e;
 }
 
@@ -377,7 +383,7 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
     std::vector<const ZVariant *> vars;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R == ctx->R && v->vw == vw) vars.push_back(v);
+        if (v->R == ctx->R && v->st == ctx->st && v->vw == vw) vars.push_back(v);
     }
     if (zmarch_possible(ctx) && !vars.empty()) {
         if (o.parts < 2) {
@@ -429,7 +435,7 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
 
 // Time `steps` steps of a tile (after `warm` untimed ones) on the stream;
 // returns milliseconds, or +inf if a launch failed.
-double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, float *&a, float *&b, int warm,
+double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, void *&a, void *&b, int warm,
                  int steps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipError_t *err)
 {
     for (int i = 0; i < warm; ++i) {
@@ -501,7 +507,15 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
         return STENCIL_EINVAL;
     if (d->nx * d->ny > ((int64_t)1 << 29)) return STENCIL_EINVAL;  // plane byte offsets are 32-bit
     if (!radius_ok(d->radius)) return STENCIL_EINVAL;
-    if (d->storage != STENCIL_F32) return STENCIL_EUNSUPPORTED;
+    if (d->storage != STENCIL_F32 && d->storage != STENCIL_F16 && d->storage != STENCIL_BF16)
+        return STENCIL_EUNSUPPORTED;
+    if (d->storage != STENCIL_F32 && d->radius < 4) return STENCIL_EUNSUPPORTED;  // 16-bit kernels: R = 4, 5
+    const double scale = d->storage_scale == 0.0 ? 1.0 : d->storage_scale;
+    {
+        int ex = 0;
+        if (!(scale > 0) || !std::isfinite(scale) || std::frexp(scale, &ex) != 0.5 || ex < -100 || ex > 100)
+            return STENCIL_EINVAL;  // a power of two, so scaling is exact
+    }
     if (!(d->h > 0) || !(d->dt > 0) || !(d->vmax > 0) || !std::isfinite(d->h) || !std::isfinite(d->dt) ||
         !std::isfinite(d->vmax))
         return STENCIL_EINVAL;
@@ -511,6 +525,9 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     if (!ctx) return STENCIL_ENOMEM;
     ctx->d = *d;
     ctx->R = d->radius;
+    ctx->st = d->storage;
+    ctx->es = d->storage == STENCIL_F32 ? 4 : 2;
+    ctx->scale = (float)scale;
     stencil_coefficients(ctx->R, ctx->cf);
     stencil_tile t = default_tile(ctx);
     if (d->tile.kind != STENCIL_TILE_AUTO) {
@@ -554,13 +571,13 @@ stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile)
     return STENCIL_OK;
 }
 
-int32_t stencil_list_tiles(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap)
+int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stencil_tile *out, int32_t cap)
 {
-    if (!radius_ok(radius) || cap < 0) return STENCIL_EINVAL;
+    if (!radius_ok(radius) || cap < 0 || storage < STENCIL_F32 || storage > STENCIL_BF16) return STENCIL_EINVAL;
     int32_t n = 0;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R != radius || v->vw != (vec4 ? 4 : 1)) continue;
+        if (v->R != radius || v->st != storage || v->vw != (vec4 ? 4 : 1)) continue;
         if (out && n < cap) {
             stencil_tile t = {};
             t.kind = STENCIL_TILE_ZMARCH;
@@ -593,14 +610,14 @@ stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!kappa || !u_cur || !u_prev || !u_next) return fail(ctx, STENCIL_EINVAL, "null field pointer");
-    const int64_t bytes = npoints(ctx) * 4;
+    const int64_t bytes = npoints(ctx) * ctx->es, kbytes = npoints(ctx) * 4;
     if (overlaps(u_cur, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "u_cur overlaps the output");
-    if (overlaps(kappa, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps the output");
+    if (overlaps2(kappa, kbytes, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps the output");
     if (u_prev != u_next && overlaps(u_prev, u_next, bytes))
         return fail(ctx, STENCIL_EALIAS, "u_prev partially overlaps the output");
-    if (ctx->tile.vw == 4 &&
-        (((uintptr_t)kappa | (uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next) & 15u))
-        return fail(ctx, STENCIL_EINVAL, "fields must be 16-byte aligned for vw = 4");
+    if (ctx->tile.vw == 4 && (((uintptr_t)kappa & 15u) ||
+                              (((uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next) & (uintptr_t)(4 * ctx->es - 1))))
+        return fail(ctx, STENCIL_EINVAL, "kappa must be 16-byte and the wavefields 4-value aligned for vw = 4");
     if (src && src->n != 0) {
         if (src->n < 0 || !src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
         if (it < 0 || it >= src->nt) return fail(ctx, STENCIL_EINVAL, "step index outside the source's samples");
@@ -701,8 +718,9 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!kappa || !scratch_a || !scratch_b || !report) return fail(ctx, STENCIL_EINVAL, "null pointer");
-    const int64_t bytes = npoints(ctx) * 4;
-    if (overlaps(scratch_a, scratch_b, bytes) || overlaps(kappa, scratch_a, bytes) || overlaps(kappa, scratch_b, bytes))
+    const int64_t bytes = npoints(ctx) * ctx->es, kbytes = npoints(ctx) * 4;
+    if (overlaps(scratch_a, scratch_b, bytes) || overlaps2(kappa, kbytes, scratch_a, bytes) ||
+        overlaps2(kappa, kbytes, scratch_b, bytes))
         return fail(ctx, STENCIL_EALIAS, "kappa and the two scratch fields must not overlap");
     if (((uintptr_t)kappa | (uintptr_t)scratch_a | (uintptr_t)scratch_b) & 15u)
         return fail(ctx, STENCIL_EINVAL, "fields must be 16-byte aligned");
@@ -749,7 +767,7 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
         hipEventDestroy(e0);
         return hip_fail(ctx, he, "hipEventCreate");
     }
-    float *a = (float *)scratch_a, *b = (float *)scratch_b;
+    void *a = scratch_a, *b = scratch_b;
     const float *k = (const float *)kappa;
     std::vector<double> table((size_t)n_rep * nC, std::numeric_limits<double>::infinity());
     hipError_t last = hipSuccess;
@@ -817,6 +835,7 @@ stencil_status stencil_sample(stencil_ctx *ctx, const void *u, const int64_t *id
                               void *stream)
 {
     if (!ctx) return STENCIL_EINVAL;
+    if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "receiver samples need FP32 storage");
     if (n < 0) return fail(ctx, STENCIL_EINVAL, "negative receiver count");
     if (n == 0) return STENCIL_OK;
     if (!u || !idx || !out) return fail(ctx, STENCIL_EINVAL, "null pointer");
@@ -832,6 +851,7 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
                                     const void *u_prev, double *grad, void *stream)
 {
     if (!ctx) return STENCIL_EINVAL;
+    if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "the adjoint needs FP32 storage");
     if (grad && (!u_next || !u_cur || !u_prev))
         return fail(ctx, STENCIL_EINVAL, "gradient accumulation needs u_next, u_cur and u_prev");
     if (grad) {
@@ -883,12 +903,13 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             delete bt;
             return STENCIL_EINVAL;
         }
-        const int64_t bytes = npoints(sh.ctx) * 4;
-        if (overlaps(sh.u_a, sh.u_b, bytes) || overlaps(sh.kappa, sh.u_a, bytes) || overlaps(sh.kappa, sh.u_b, bytes)) {
+        const int64_t ub = npoints(sh.ctx) * sh.ctx->es, kb = npoints(sh.ctx) * 4;
+        if (overlaps(sh.u_a, sh.u_b, ub) || overlaps2(sh.kappa, kb, sh.u_a, ub) || overlaps2(sh.kappa, kb, sh.u_b, ub)) {
             delete bt;
             return STENCIL_EALIAS;
         }
-        if (sh.ctx->tile.vw == 4 && (((uintptr_t)sh.kappa | (uintptr_t)sh.u_a | (uintptr_t)sh.u_b) & 15u)) {
+        if (sh.ctx->tile.vw == 4 &&
+            (((uintptr_t)sh.kappa & 15u) || (((uintptr_t)sh.u_a | (uintptr_t)sh.u_b) & (uintptr_t)(4 * sh.ctx->es - 1)))) {
             delete bt;
             return STENCIL_EINVAL;
         }
@@ -897,7 +918,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             return STENCIL_EINVAL;
         }
         if (sh.src.n > 0) bt->nt_min = std::min(bt->nt_min, sh.src.nt);
-        bt->shots.push_back({sh.ctx, (const float *)sh.kappa, (float *)sh.u_a, (float *)sh.u_b, sh.src,
+        bt->shots.push_back({sh.ctx, (const float *)sh.kappa, sh.u_a, sh.u_b, sh.src,
                              tiles ? tiles[i] : sh.ctx->tile});
     }
     // Group the z-march shots by compiled kernel (tile shape) and XCD order.
@@ -907,7 +928,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             bt->solo.push_back(i);
             continue;
         }
-        const ZVariant *v = find_variant(bt->shots[i].ctx->R, t);
+        const ZVariant *v = find_variant(bt->shots[i].ctx, t);
         bool placed = false;
         for (auto &g : bt->groups)
             if (g.v == v && g.xcd == t.xcd) {
@@ -926,7 +947,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
         int64_t blocks = 0;
         for (int i = 0; i < n; ++i) {
             const auto &sh = bt->shots[i];
-            if (sh.tile.kind != STENCIL_TILE_ZMARCH || find_variant(sh.ctx->R, sh.tile) != g.v || sh.tile.xcd != g.xcd)
+            if (sh.tile.kind != STENCIL_TILE_ZMARCH || find_variant(sh.ctx, sh.tile) != g.v || sh.tile.xcd != g.xcd)
                 continue;
             const stencil_desc &d = sh.ctx->d;
             SweepArgs a = {};
@@ -935,6 +956,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             a.ny = (int)d.ny;
             a.nz = (int)d.nz;
             for (int m = 0; m <= sh.ctx->R; ++m) a.c[m] = sh.ctx->cf[m];
+            a.scale = sh.ctx->scale;
             a.dz = sh.tile.dz;
             a.gx = (int)((d.nx + (int64_t)sh.tile.bx * sh.tile.vw - 1) / ((int64_t)sh.tile.bx * sh.tile.vw));
             a.gy = (int)((d.ny + (int64_t)sh.tile.by * sh.tile.ry - 1) / ((int64_t)sh.tile.by * sh.tile.ry));
@@ -1022,14 +1044,15 @@ stencil_status stencil_batch_step(stencil_batch *bt, int64_t it, void *stream)
     }
     for (size_t i = 0; i < bt->shots.size(); ++i) {
         const auto &sh = bt->shots[i];
-        const float *uc = par ? sh.u_b : sh.u_a;
-        float *up = par ? sh.u_a : sh.u_b;
+        const void *uc = par ? sh.u_b : sh.u_a;
+        void *up = par ? sh.u_a : sh.u_b;
         const bool solo = sh.tile.kind != STENCIL_TILE_ZMARCH;
         if (solo) {
             hipError_t e = enqueue_step(sh.ctx, sh.tile, sh.kappa, uc, up, up, it, sh.src.n ? &sh.src : nullptr, s);
             if (e != hipSuccess) return STENCIL_EDEVICE;
         } else if (sh.src.n > 1) {
-            hipError_t e = p1310::launch_inject(up, sh.kappa, npoints(sh.ctx), sh.src.idx, sh.src.amp, sh.src.n, it, s);
+            hipError_t e = p1310::launch_inject(sh.ctx->st, up, sh.kappa, npoints(sh.ctx), sh.src.idx, sh.src.amp,
+                                                sh.src.n, it, sh.ctx->scale, s);
             if (e != hipSuccess) return STENCIL_EDEVICE;
         }
     }
@@ -1152,6 +1175,21 @@ stencil_status stencil_batch_tune(const stencil_shot *shots, int32_t n, const st
             for (int c = 0; c < nC && c < o.table_cap; ++c) o.table[(size_t)r * o.table_cap + c] = table[(size_t)r * nC + c];
     if (o.candidates)
         for (int c = 0; c < nC && c < o.table_cap; ++c) o.candidates[c] = cand_key[c];
+    return STENCIL_OK;
+}
+
+stencil_status stencil_convert(stencil_ctx *ctx, const void *src, void *dst, int32_t to_storage, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!src || !dst) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    const int64_t ub = npoints(ctx) * ctx->es, fb = npoints(ctx) * 4;
+    if (overlaps2(src, to_storage ? fb : ub, dst, to_storage ? ub : fb))
+        return fail(ctx, STENCIL_EALIAS, "src and dst overlap");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = p1310::launch_convert(ctx->st, src, dst, npoints(ctx), ctx->scale, to_storage ? 1 : 0,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "convert launch");
     return STENCIL_OK;
 }
 

@@ -12,10 +12,10 @@ constexpr int kMaxRadius = 5;
 
 // Arguments of one sweep launch (passed by value as the kernel argument).
 struct SweepArgs {
-    const float *kappa;      // [nz][ny][nx]
-    const float *ucur;       // u^n
-    const float *uprev;      // u^{n-1}
-    float *unext;            // u^{n+1} (may be uprev: in-place update)
+    const float *kappa;      // [nz][ny][nx], FP32
+    const void *ucur;        // u^n (storage type of the variant)
+    const void *uprev;       // u^{n-1}
+    void *unext;             // u^{n+1} (may be uprev: in-place update)
     int nx, ny, nz;
     int dz;                  // planes per workgroup (z-march)
     int gx, gy, gz;          // tiles along x, y and z-chunks
@@ -25,11 +25,15 @@ struct SweepArgs {
     const float *src_amp;
     int nsrc;
     int64_t it;
+    float scale;             // storage scale: source amplitudes are multiplied by it
 };
+
+// Wavefield storage types (stencil_storage).
+constexpr int kF32 = 0, kF16 = 1, kBF16 = 2;
 
 // One compiled z-march instantiation.
 struct ZVariant {
-    int R, bx, by, ry, vw, pf;
+    int R, bx, by, ry, vw, pf, st;
     void (*kernel)(SweepArgs);
     void (*batch_kernel)(const SweepArgs *, const int *, int, int, int64_t);
     int threads;
@@ -44,9 +48,11 @@ const ZVariant *zmarch_variant(int i);
 hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s);
 hipError_t launch_zmarch_batch(const ZVariant &v, const SweepArgs *shots, const int *wg_begin, int nshots,
                                int total_blocks, int xcd, int64_t it, hipStream_t s);
-hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
-hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
-                         const float *amp, int nsrc, int64_t it, hipStream_t s);
+hipError_t launch_plain(int R, int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
+hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, const int64_t *idx,
+                         const float *amp, int nsrc, int64_t it, float scale, hipStream_t s);
+hipError_t launch_convert(int st, const void *src, void *dst, int64_t n, float scale, int to_storage,
+                          hipStream_t s);
 hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, double h, hipStream_t s);
 hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, double h, hipStream_t s);
 hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s);

@@ -7,9 +7,9 @@ namespace p1310 {
 const ZVariant *zmarch_table_r3(int *n);
 const ZVariant *zmarch_table_r4(int *n);
 const ZVariant *zmarch_table_r5(int *n);
-hipError_t launch_plain_r3(int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
-hipError_t launch_plain_r4(int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
-hipError_t launch_plain_r5(int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
+hipError_t launch_plain_r3(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
+hipError_t launch_plain_r4(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
+hipError_t launch_plain_r5(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
 
 namespace {
 
@@ -55,8 +55,9 @@ __global__ void __launch_bounds__(256) kappa_m_kernel(const float *m, float *kap
 // Several point sources, one thread per source. Repeated indices are added
 // by the thread of their first occurrence, in index order, so the result is
 // the same as adding the sources one after another.
-__global__ void __launch_bounds__(256) inject_kernel(float *u, const float *kappa, int64_t n_points,
-                                                     const int64_t *idx, const float *amp, int nsrc, int64_t it)
+template <typename ST>
+__global__ void __launch_bounds__(256) inject_kernel(ST *u, const float *kappa, int64_t n_points, const int64_t *idx,
+                                                     const float *amp, int nsrc, int64_t it, float scale)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nsrc) return;
@@ -65,10 +66,26 @@ __global__ void __launch_bounds__(256) inject_kernel(float *u, const float *kapp
     for (int k = 0; k < j; ++k)
         if (idx[k] == p) return;  // an earlier source owns this point
     const float kp = kappa[p];
-    float v = u[p];
+    float v = (float)u[p];
     for (int k = j; k < nsrc; ++k)
-        if (idx[k] == p) v = __builtin_fmaf(kp, amp[it * nsrc + k], v);
-    u[p] = v;
+        if (idx[k] == p) v = __builtin_fmaf(kp, amp[it * nsrc + k] * scale, v);
+    u[p] = (ST)v;
+}
+
+// FP32 field <-> storage: to storage dst = round(src * scale) (nearest even),
+// back dst = src / scale (scale is a power of two, so both scalings are exact).
+template <typename ST>
+__global__ void __launch_bounds__(256) convert_kernel(const void *src, void *dst, int64_t n, float scale,
+                                                      int to_storage)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float inv = 1.0f / scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (to_storage)
+            ((ST *)dst)[i] = (ST)(((const float *)src)[i] * scale);
+        else
+            ((float *)dst)[i] = (float)((const ST *)src)[i] * inv;
+    }
 }
 
 // Receiver samples: out[j] = u[idx[j]] (0 for an index outside the grid).
@@ -215,21 +232,58 @@ hipError_t launch_zmarch_batch(const ZVariant &v, const SweepArgs *shots, const 
     return hipGetLastError();
 }
 
-hipError_t launch_plain(int R, int bx, int by, int bz, const SweepArgs &a, hipStream_t s)
+hipError_t launch_plain(int R, int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s)
 {
     switch (R) {
-    case 3: return launch_plain_r3(bx, by, bz, a, s);
-    case 4: return launch_plain_r4(bx, by, bz, a, s);
-    case 5: return launch_plain_r5(bx, by, bz, a, s);
+    case 3: return launch_plain_r3(st, bx, by, bz, a, s);
+    case 4: return launch_plain_r4(st, bx, by, bz, a, s);
+    case 5: return launch_plain_r5(st, bx, by, bz, a, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_inject(float *u, const float *kappa, int64_t n_points, const int64_t *idx,
-                         const float *amp, int nsrc, int64_t it, hipStream_t s)
+hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, const int64_t *idx,
+                         const float *amp, int nsrc, int64_t it, float scale, hipStream_t s)
 {
-    hipLaunchKernelGGL(inject_kernel, dim3((nsrc + 255) / 256), dim3(256), 0, s, u, kappa, n_points, idx, amp, nsrc,
-                       it);
+    const dim3 grid((nsrc + 255) / 256), block(256);
+    switch (st) {
+    case kF32:
+        hipLaunchKernelGGL(inject_kernel<float>, grid, block, 0, s, (float *)u, kappa, n_points, idx, amp, nsrc, it,
+                           scale);
+        break;
+    case kF16:
+        hipLaunchKernelGGL(inject_kernel<_Float16>, grid, block, 0, s, (_Float16 *)u, kappa, n_points, idx, amp,
+                           nsrc, it, scale);
+        break;
+    case kBF16:
+        hipLaunchKernelGGL(inject_kernel<__bf16>, grid, block, 0, s, (__bf16 *)u, kappa, n_points, idx, amp, nsrc,
+                           it, scale);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int st, const void *src, void *dst, int64_t n, float scale, int to_storage, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    switch (st) {
+    case kF32:
+        hipLaunchKernelGGL(convert_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, scale,
+                           to_storage);
+        break;
+    case kF16:
+        hipLaunchKernelGGL(convert_kernel<_Float16>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, scale,
+                           to_storage);
+        break;
+    case kBF16:
+        hipLaunchKernelGGL(convert_kernel<__bf16>, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, scale,
+                           to_storage);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -11,11 +11,30 @@ namespace p1310 {
 #define P1310_CAT2(a, b) a##b
 #define P1310_CAT(a, b) P1310_CAT2(a, b)
 
-// (BX, BY, RY, VW, PF) of every z-march instantiation.
-#define ZV(BX, BY, RY, VW, PF)                                                                  \
-    {RADIUS, BX, BY, RY, VW, PF, zmarch_kernel<RADIUS, BX, BY, RY, VW, PF>,                     \
-     zmarch_batch_kernel<RADIUS, BX, BY, RY, VW, PF>, BX * BY,                                  \
-     (int)(2 * (((BY * RY + 2 * RADIUS) * (BX * VW + 2 * ((VW == 1) ? RADIUS : ((RADIUS + VW - 1) / VW) * VW))) + VW) * 4)},
+// Storage type tags of the table (kF32 / kF16 / kBF16) and their C++ types.
+#define ST_kF32 float
+#define ST_kF16 _Float16
+#define ST_kBF16 __bf16
+
+// LDS bytes of a (BX, BY, RY, VW) tile: two planes of (TY + 2R) x (TX + 2HX) FP32 values.
+#define ZV_LDS(BX, BY, RY, VW)                                                                   \
+    (int)(2 * (((BY * RY + 2 * RADIUS) * (BX * VW + 2 * ((VW == 1) ? RADIUS : ((RADIUS + VW - 1) / VW) * VW))) + VW) * 4)
+
+// One z-march instantiation: (BX, BY, RY, VW, PF) and the storage tag.
+#define ZVS(BX, BY, RY, VW, PF, STT)                                                             \
+    {RADIUS, BX, BY, RY, VW, PF, STT, zmarch_kernel<RADIUS, BX, BY, RY, VW, PF, ST_##STT>,       \
+     zmarch_batch_kernel<RADIUS, BX, BY, RY, VW, PF, ST_##STT>, BX * BY, ZV_LDS(BX, BY, RY, VW)},
+#define ZV(BX, BY, RY, VW, PF) ZVS(BX, BY, RY, VW, PF, kF32)
+
+// 16-bit wavefield storage: a smaller set of shapes, radii 4 and 5.
+#if RADIUS >= 4
+#define ZV16(STT)                                                                                \
+    ZVS(16, 8, 1, 4, 0, STT) ZVS(16, 8, 2, 4, 0, STT) ZVS(32, 8, 1, 4, 0, STT)                  \
+    ZVS(32, 4, 2, 4, 0, STT) ZVS(64, 4, 1, 4, 0, STT) ZVS(64, 4, 2, 4, 0, STT)                  \
+    ZVS(16, 16, 1, 4, 0, STT) ZVS(64, 4, 1, 4, 1, STT) ZVS(64, 4, 1, 1, 0, STT)
+#else
+#define ZV16(STT)
+#endif
 
 static const ZVariant kTable[] = {
     ZV(16, 4, 1, 4, 0) ZV(16, 4, 2, 4, 0)
@@ -29,6 +48,7 @@ static const ZVariant kTable[] = {
     ZV(16, 4, 2, 4, 1) ZV(16, 8, 1, 4, 1) ZV(16, 8, 2, 4, 1) ZV(16, 16, 1, 4, 1)
     ZV(32, 4, 2, 4, 1) ZV(32, 8, 1, 4, 1) ZV(64, 4, 1, 4, 1)
     ZV(64, 4, 1, 1, 0) ZV(64, 4, 2, 1, 0) ZV(32, 8, 2, 1, 0) ZV(64, 8, 1, 1, 0)
+    ZV16(kF16) ZV16(kBF16)
 };
 
 const ZVariant *P1310_CAT(zmarch_table_r, RADIUS)(int *n)
@@ -37,11 +57,18 @@ const ZVariant *P1310_CAT(zmarch_table_r, RADIUS)(int *n)
     return kTable;
 }
 
-hipError_t P1310_CAT(launch_plain_r, RADIUS)(int bx, int by, int bz, const SweepArgs &a, hipStream_t s)
+hipError_t P1310_CAT(launch_plain_r, RADIUS)(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s)
 {
     dim3 block(bx, by, bz);
     dim3 grid((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, (a.nz + bz - 1) / bz);
-    hipLaunchKernelGGL(plain_kernel<RADIUS>, grid, block, 0, s, a);
+    switch (st) {
+    case kF32: hipLaunchKernelGGL((plain_kernel<RADIUS, float>), grid, block, 0, s, a); break;
+#if RADIUS >= 4
+    case kF16: hipLaunchKernelGGL((plain_kernel<RADIUS, _Float16>), grid, block, 0, s, a); break;
+    case kBF16: hipLaunchKernelGGL((plain_kernel<RADIUS, __bf16>), grid, block, 0, s, a); break;
+#endif
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

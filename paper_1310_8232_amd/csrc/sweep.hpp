@@ -10,7 +10,7 @@
 //   at a source point: u^{n+1} = fma(kappa, amp, u^{n+1})
 // where x+/x- = u(p +- m e_x) etc., taken as 0 outside the grid.
 //
-// Included by kernels_r<R>.hip, each of which instantiates one radius.
+// Included by kernels_radius.hip, compiled once per radius.
 #pragma once
 
 #include "internal.h"
@@ -68,6 +68,47 @@ __device__ __forceinline__ Vec<VW> vzero()
     return v;
 }
 
+// Wavefield storage: FP32, or 16-bit (FP16 / BF16) widened to FP32 on load
+// and rounded to nearest even once on store. kappa is always FP32.
+template <typename ST>
+struct StorageBytes {
+    static constexpr int value = sizeof(ST);
+};
+
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
+template <typename ST, int VW, int AUX>
+__device__ __forceinline__ Vec<VW> uload(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(ST) == 4) {
+        return bload<VW, AUX>(r, voff, soff);
+    } else if constexpr (VW == 4) {
+        typedef ST s4 __attribute__((ext_vector_type(4)));
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const s4 h = __builtin_bit_cast(s4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
+        return __builtin_bit_cast(Vec<4>, __builtin_convertvector(h, f4));
+    } else {
+        Vec<1> v;
+        v.a[0] = (float)__builtin_bit_cast(ST, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX));
+        return v;
+    }
+}
+
+template <typename ST, int VW, int AUX>
+__device__ __forceinline__ void ustore(const Vec<VW> &v, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (sizeof(ST) == 4) {
+        bstore<VW, AUX>(v, r, voff, soff);
+    } else if constexpr (VW == 4) {
+        typedef ST s4 __attribute__((ext_vector_type(4)));
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const s4 h = __builtin_convertvector(__builtin_bit_cast(f4, v), s4);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, h), r, voff, soff, AUX);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (ST)v.a[0]), r, voff, soff, AUX);
+    }
+}
+
 // Workgroup barrier that orders LDS traffic only: outstanding global loads
 // (the next plane's prefetch) stay in flight across it.
 __device__ __forceinline__ void lds_barrier()
@@ -101,9 +142,10 @@ __device__ __forceinline__ int xcd_order(int b, int nblk, int nxcd)
 // The plane loop is unrolled by Q so that every queue slot index is a
 // compile-time constant (no register moves for the shift).
 // ---------------------------------------------------------------------------
-template <int R, int BX, int BY, int RY, int VW, int PF>
+template <int R, int BX, int BY, int RY, int VW, int PF, typename ST>
 __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
 {
+    constexpr int ES = StorageBytes<ST>::value;  // bytes per wavefield value
     constexpr int NT = BX * BY;
     constexpr int TX = BX * VW, TY = BY * RY;
     constexpr int HX = (VW == 1) ? R : ((R + VW - 1) / VW) * VW;  // x halo, whole vectors
@@ -131,23 +173,28 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     const int zlo = max(z0 - R, 0);
     const int zhi = min(z1 + R, a.nz);
     const int64_t plane = (int64_t)a.nx * a.ny;
-    const uint32_t pbytes = (uint32_t)(plane * 4);
+    const uint32_t pbytes = (uint32_t)(plane * ES);  // one plane of a wavefield
+    const uint32_t kbytes = (uint32_t)(plane * 4);   // one plane of kappa
     const uint32_t win = (uint32_t)(zhi - zlo) * pbytes;
-    const rsrc_t rc = make_rsrc(a.ucur + zlo * plane, win);
-    const rsrc_t rp = make_rsrc(a.uprev + zlo * plane, win);
-    const rsrc_t rn = make_rsrc(a.unext + zlo * plane, win);
-    const rsrc_t rk = make_rsrc(a.kappa + zlo * plane, win);
+    const uint32_t kwin = (uint32_t)(zhi - zlo) * kbytes;
+    const rsrc_t rc = make_rsrc((const float *)((const char *)a.ucur + zlo * plane * ES), win);
+    const rsrc_t rp = make_rsrc((const float *)((const char *)a.uprev + zlo * plane * ES), win);
+    const rsrc_t rn = make_rsrc((const float *)((char *)a.unext + zlo * plane * ES), win);
+    const rsrc_t rk = make_rsrc(a.kappa + zlo * plane, kwin);
 
     // ---- this thread's points and halo items (same offsets every plane) ----
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = tid / BX;
     const int xs = x0 + tx * VW;
     const int yb = y0 + ty * RY;
-    uint32_t coff[RY];
+    uint32_t coff[RY];  // wavefield byte offsets of this thread's rows
+    uint32_t koff[RY];  // kappa byte offsets (the same as coff for FP32 storage)
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int y = yb + j;
-        coff[j] = (xs < a.nx && y < a.ny) ? (uint32_t)(y * a.nx + xs) * 4u : kOOB;
+        const bool in = xs < a.nx && y < a.ny;
+        coff[j] = in ? (uint32_t)(y * a.nx + xs) * (uint32_t)ES : kOOB;
+        koff[j] = in ? (uint32_t)(y * a.nx + xs) * 4u : kOOB;
     }
     uint32_t hg[NHI];
     int hl[NHI];
@@ -175,7 +222,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
         }
         hl[i] = valid ? lrow * LW + lcol : LROWS * LW;
         hg[i] = (valid && gxx >= 0 && gxx < a.nx && gyy >= 0 && gyy < a.ny)
-                    ? (uint32_t)(gyy * a.nx + gxx) * 4u : kOOB;
+                    ? (uint32_t)(gyy * a.nx + gxx) * (uint32_t)ES : kOOB;
     }
 
     // ---- fused single source ------------------------------------------------
@@ -189,7 +236,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
             const int sy = rem / a.nx, sx = rem - (rem / a.nx) * a.nx;
             if (sz >= z0 && sz < z1) {
                 s_z = sz;
-                s_amp = a.src_amp[a.it];
+                s_amp = a.src_amp[a.it] * a.scale;
                 const int dj = sy - yb, de = sx - xs;
                 if (dj >= 0 && dj < RY && de >= 0 && de < VW) {
                     s_j = dj;
@@ -207,7 +254,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
         if (p >= 0 && p < a.nz) {
             const uint32_t so = (uint32_t)(p - zlo) * pbytes;
 #pragma unroll
-            for (int j = 0; j < RY; ++j) dst[j] = bload<VW, 0>(rc, coff[j], so);
+            for (int j = 0; j < RY; ++j) dst[j] = uload<ST, VW, 0>(rc, coff[j], so);
         } else {
 #pragma unroll
             for (int j = 0; j < RY; ++j) dst[j] = vzero<VW>();
@@ -216,14 +263,15 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     auto load_halo = [&](V (&dst)[NHI], int p) {
         const uint32_t so = (uint32_t)(p - zlo) * pbytes;
 #pragma unroll
-        for (int i = 0; i < NHI; ++i) dst[i] = bload<VW, 0>(rc, hg[i], so);
+        for (int i = 0; i < NHI; ++i) dst[i] = uload<ST, VW, 0>(rc, hg[i], so);
     };
     auto load_uk = [&](V (&du)[RY], V (&dk)[RY], int p) {
         const uint32_t so = (uint32_t)(p - zlo) * pbytes;
+        const uint32_t sk = (uint32_t)(p - zlo) * kbytes;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            du[j] = bload<VW, kNT>(rp, coff[j], so);
-            dk[j] = bload<VW, kNT>(rk, coff[j], so);
+            du[j] = uload<ST, VW, kNT>(rp, coff[j], so);
+            dk[j] = bload<VW, kNT>(rk, koff[j], sk);
         }
     };
 
@@ -244,6 +292,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
             const int sc = (j + R) % Q;
             float *buf = lds + (j & 1) * LBUF;
             const uint32_t so = (uint32_t)(z - zlo) * pbytes;
+            const uint32_t sk = (uint32_t)(z - zlo) * kbytes;
 
             // u^{n-1} and kappa of plane z (issued before the prefetch so
             // that waiting for them does not wait for the prefetch).
@@ -257,8 +306,8 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
             } else {
 #pragma unroll
                 for (int jj = 0; jj < RY; ++jj) {
-                    up[jj] = bload<VW, kNT>(rp, coff[jj], so);
-                    kp[jj] = bload<VW, kNT>(rk, coff[jj], so);
+                    up[jj] = uload<ST, VW, kNT>(rp, coff[jj], so);
+                    kp[jj] = bload<VW, kNT>(rk, koff[jj], sk);
                 }
             }
 
@@ -326,23 +375,23 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
                             out[jj].a[e] = __builtin_fmaf(kp[jj].a[e], s_amp, out[jj].a[e]);
             }
 #pragma unroll
-            for (int jj = 0; jj < RY; ++jj) bstore<VW, kNT>(out[jj], rn, coff[jj], so);
+            for (int jj = 0; jj < RY; ++jj) ustore<ST, VW, kNT>(out[jj], rn, coff[jj], so);
         }
     }
 }
 
-template <int R, int BX, int BY, int RY, int VW, int PF>
+template <int R, int BX, int BY, int RY, int VW, int PF, typename ST>
 __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
 {
     int b = blockIdx.x;
     if (a.xcd > 1) b = xcd_order(b, gridDim.x, a.xcd);
-    zmarch_body<R, BX, BY, RY, VW, PF>(a, b);
+    zmarch_body<R, BX, BY, RY, VW, PF, ST>(a, b);
 }
 
 // Several grids (shots) in one launch: the launch grid concatenates every
 // shot's workgroups; wg_begin[s] is the first workgroup of shot s. Each shot
 // keeps its own sizes, march depth, fields and source; `it` is the step.
-template <int R, int BX, int BY, int RY, int VW, int PF>
+template <int R, int BX, int BY, int RY, int VW, int PF, typename ST>
 __global__ void __launch_bounds__(BX * BY) zmarch_batch_kernel(const SweepArgs *shots, const int *wg_begin,
                                                                int nshots, int xcd, int64_t it)
 {
@@ -352,14 +401,14 @@ __global__ void __launch_bounds__(BX * BY) zmarch_batch_kernel(const SweepArgs *
     while (s + 1 < nshots && wg_begin[s + 1] <= b) ++s;
     SweepArgs a = shots[s];
     a.it = it;
-    zmarch_body<R, BX, BY, RY, VW, PF>(a, b - wg_begin[s]);
+    zmarch_body<R, BX, BY, RY, VW, PF, ST>(a, b - wg_begin[s]);
 }
 
 // ---------------------------------------------------------------------------
 // Plain tiling: one thread per point, a bx x by x bz workgroup per block of
 // the grid, every tap read from memory (caches only). Same arithmetic order.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, typename ST>
 __global__ void __launch_bounds__(1024) plain_kernel(SweepArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,24 +418,24 @@ __global__ void __launch_bounds__(1024) plain_kernel(SweepArgs a)
     const int64_t sy = a.nx;
     const int64_t sz = (int64_t)a.nx * a.ny;
     const int64_t p = (int64_t)z * sz + (int64_t)y * sy + x;
-    const float *u = a.ucur;
-    const float u0 = u[p];
+    const ST *u = (const ST *)a.ucur;
+    const float u0 = (float)u[p];
     float acc = a.c[0] * u0;
 #pragma unroll
     for (int m = 1; m <= R; ++m) {
-        const float xp = (x + m < a.nx) ? u[p + m] : 0.0f;
-        const float xm = (x - m >= 0) ? u[p - m] : 0.0f;
-        const float yp = (y + m < a.ny) ? u[p + m * sy] : 0.0f;
-        const float ym = (y - m >= 0) ? u[p - m * sy] : 0.0f;
-        const float zp = (z + m < a.nz) ? u[p + m * sz] : 0.0f;
-        const float zm = (z - m >= 0) ? u[p - m * sz] : 0.0f;
+        const float xp = (x + m < a.nx) ? (float)u[p + m] : 0.0f;
+        const float xm = (x - m >= 0) ? (float)u[p - m] : 0.0f;
+        const float yp = (y + m < a.ny) ? (float)u[p + m * sy] : 0.0f;
+        const float ym = (y - m >= 0) ? (float)u[p - m * sy] : 0.0f;
+        const float zp = (z + m < a.nz) ? (float)u[p + m * sz] : 0.0f;
+        const float zm = (z - m >= 0) ? (float)u[p - m * sz] : 0.0f;
         const float s = ((xp + xm) + (yp + ym)) + (zp + zm);
         acc = __builtin_fmaf(a.c[m], s, acc);
     }
     const float k = a.kappa[p];
-    float o = __builtin_fmaf(k, acc, __builtin_fmaf(2.0f, u0, -a.uprev[p]));
-    if (a.nsrc == 1 && a.src_idx[0] == p) o = __builtin_fmaf(k, a.src_amp[a.it], o);
-    a.unext[p] = o;
+    float o = __builtin_fmaf(k, acc, __builtin_fmaf(2.0f, u0, -(float)((const ST *)a.uprev)[p]));
+    if (a.nsrc == 1 && a.src_idx[0] == p) o = __builtin_fmaf(k, a.src_amp[a.it] * a.scale, o);
+    ((ST *)a.unext)[p] = (ST)o;
 }
 
 }  // namespace p1310

@@ -97,10 +97,23 @@ def test_init_validation():
     assert e.value.status == p.EUNSTABLE
 
 
-def test_unsupported_storage():
-    d = p.StencilDesc(16, 16, 16, 4, 7, 10.0, 0.001, 2000.0, 0, p.StencilTile())
+def test_storage_validation():
+    d = p.StencilDesc(16, 16, 16, 4, 7, 10.0, 0.001, 2000.0, 0, p.StencilTile(), 1.0)
     out = ctypes.c_void_p()
     assert p._lib.stencil_init(ctypes.byref(d), ctypes.byref(out)) == p.EUNSUPPORTED
+    for st in ("f16", "bf16"):
+        ctx = _init(storage=st, storage_scale=1024.0)
+        assert p.stencil_get_tile(ctx).vw == 4
+        p.stencil_destroy(ctx)
+        with pytest.raises(p.StencilError) as e:
+            _init(storage=st, radius=3)  # 16-bit kernels exist for R = 4, 5
+        assert e.value.status == p.EUNSUPPORTED
+        with pytest.raises(p.StencilError) as e:
+            _init(storage=st, storage_scale=3.0)  # not a power of two
+        assert e.value.status == p.EINVAL
+        assert len(p.stencil_list_tiles(4, True, st)) >= 5
+        assert len(p.stencil_list_tiles(5, False, st)) >= 1
+    assert len(p.stencil_list_tiles(3, True, "f16")) == 0
 
 
 def test_tiles_default_set_and_reject():
