@@ -321,6 +321,73 @@ def precision_bench(args) -> int:
     return 0
 
 
+def paper_bench(args) -> int:
+    """The paper's blocksize-search experiments on the GPU tile space, at its
+    per-process shapes and order (R = 5): exhaustive sweep (Section 3.5),
+    repeated searches per policy with MinTime / ActualTime / gap and the time
+    of a 448-step run with the chosen tile (Tables 4-5), and the P-part budget
+    sweep against the exhaustive best (Section 3.7, Table 6)."""
+    import statistics
+
+    import torch
+
+    import paper_1310_8232_amd as p
+    import workloads
+
+    iters = 448  # the paper's iteration count
+    dev = torch.device("cuda:0")
+    shapes = [(200, 200, 800), (300, 300, 800), (250, 250, 1500)]
+    if args.paper_shapes:
+        shapes = [tuple(int(v) for v in sh.split("x")) for sh in args.paper_shapes.split(",")]
+    out = {}
+    for (nx, ny, nz) in shapes:
+        c = workloads.config_layered(nx, ny, nz, nt=iters, radius=5)
+        prop = p.Propagator(torch.from_numpy(c["v"]).to(dev), c["h"], c["dt"], 5, vmax=c["vmax"])
+        idx = torch.tensor(c["src_idx"], dtype=torch.int64, device=dev)
+        amp = torch.from_numpy(c["amp"].reshape(-1, 1)).to(dev)
+        src = p.make_src(idx, amp)
+
+        def total_ms():
+            a, b = prop.zeros(), prop.zeros()
+            ms, _, _ = time_steps(prop, a, b, iters, 0, src, torch.cuda.current_stream())
+            return ms
+
+        key = f"{nx}x{ny}x{nz}"
+        rec = {}
+        rep, _, _ = prop.tune(n_iter=args.tune_iter, n_rep=1, parts=0, include_plain=True)
+        best = total_ms()
+        rec["exhaustive"] = {"n_candidates": rep["n_candidates"], "tile": rep["tile"], "seconds": rep["seconds"],
+                             "total_ms_448": round(best, 3)}
+        pol = {}
+        for policy in ("ob", "min", "worst", "avg"):
+            runs = []
+            for _ in range(args.paper_repeats):
+                rep, _, _ = prop.tune(policy=policy, n_iter=args.tune_iter, n_rep=3, parts=5)
+                runs.append({"tile": rep["tile"], "min_time_ms": round(rep["min_time_ms"], 4),
+                             "actual_time_ms": round(rep["actual_time_ms"], 4), "gap": round(rep["gap"], 5),
+                             "n_candidates": rep["n_candidates"], "total_ms_448": round(total_ms(), 3)})
+            tot = [r["total_ms_448"] for r in runs]
+            pol[policy] = {"runs": runs, "best": min(tot), "avg": round(statistics.mean(tot), 3), "worst": max(tot),
+                           "std": round(statistics.pstdev(tot), 4),
+                           "mean_abs_gap": round(statistics.mean(abs(r["gap"]) for r in runs), 5)}
+        rec["policies"] = pol
+        sweep = []
+        for P in (2, 3, 4, 5, 6):
+            rep, _, _ = prop.tune(policy="worst", n_iter=args.tune_iter, n_rep=3, parts=P)
+            t = total_ms()
+            sweep.append({"P": P, "n_candidates": rep["n_candidates"], "search_s": round(rep["seconds"], 3),
+                          "tile": rep["tile"], "total_ms_448": round(t, 3),
+                          "vs_exhaustive": round(t / best - 1.0, 4)})
+        rec["budget_sweep"] = sweep
+        out[key] = rec
+        print(f"bench: paper experiments {key} done", file=sys.stderr, flush=True)
+        del prop
+        torch.cuda.empty_cache()
+    print(json.dumps({"paper_experiments": out, "radius": 5, "iterations": iters,
+                      "repeats_per_policy": args.paper_repeats}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,7 +403,9 @@ def main(argv=None):
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision"), default="sweep",
+    ap.add_argument("--paper-repeats", type=int, default=5, help="searches per policy (paper workload)")
+    ap.add_argument("--paper-shapes", type=str, default="", help="e.g. 200x200x800,300x300x800")
+    ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision", "paper"), default="sweep",
                     help="sweep: the autotuned step (default); gradient: misfit + adjoint gradient; "
                          "batch: 16 uneven shots")
     ap.add_argument("--nt", type=int, default=0, help="time steps of the gradient workload (default 500)")
@@ -367,6 +436,8 @@ def main(argv=None):
         return batch_bench(args)
     if args.workload == "precision":
         return precision_bench(args)
+    if args.workload == "paper":
+        return paper_bench(args)
     n = args.n
     nt = args.warmup + args.steps
     t0 = time.perf_counter()
