@@ -63,7 +63,8 @@ typedef enum { STENCIL_F32 = 0, STENCIL_F16 = 1, STENCIL_BF16 = 2 } stencil_stor
 typedef enum {
     STENCIL_TILE_AUTO = 0,   /* the context's current tile (tuned, cached or built-in default) */
     STENCIL_TILE_PLAIN = 1,  /* plain tiling: one thread per point, workgroup bx*by*dz, taps read from memory */
-    STENCIL_TILE_ZMARCH = 2  /* xy tile staged in LDS, register queue marching dz planes along z */
+    STENCIL_TILE_ZMARCH = 2, /* xy tile staged in LDS, register queue marching dz planes along z */
+    STENCIL_TILE_ZMARCH2 = 3 /* two leapfrog steps per launch (blocking in time): see stencil_step2 */
 } stencil_tile_kind;
 
 /* The GPU form of the paper's blocksize (bi, bj, bk). For ZMARCH a workgroup
@@ -123,6 +124,10 @@ typedef struct {
     double *table;           /* optional out: [n_rep][table_cap] times in ms (row-major) */
     stencil_tile *candidates;/* optional out: [table_cap] candidate tiles in timing order */
     int32_t table_cap;
+    int32_t temporal;        /* 0/1 = one-step tiles (the context's tile); 2 = two-step tiles (its tile2,
+                                times still per n_iter steps, n_iter rounded up to even) */
+    void *scratch_c;         /* two-step search: two more scratch fields of the grid's shape */
+    void *scratch_d;
 } stencil_tune_opts;
 
 typedef struct {
@@ -158,6 +163,17 @@ stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void 
  * must not overlap u_cur or kappa (EALIAS). Same traffic as the in-place form. */
 stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
                                void *u_next, int64_t it, const stencil_src *src, void *stream);
+
+/* Two leapfrog steps in one launch (blocking in time as well as in space):
+ * reads u_cur = u^{it}, u_prev = u^{it-1}, kappa; writes u^{it+1} to u_next
+ * and u^{it+2} to u_next2, with the sources of steps it and it+1. The four
+ * wavefields must be distinct and must not overlap (EALIAS): the inputs are
+ * read around every tile by its neighbours while the outputs are written.
+ * At most one source (EUNSUPPORTED otherwise); it+1 < src->nt (EINVAL).
+ * Results are bit-identical to two stencil_step calls. Uses the context's
+ * two-step tile; FP32 storage. Capture-safe. */
+stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
+                             void *u_next, void *u_next2, int64_t it, const stencil_src *src, void *stream);
 
 /* One leapfrog step n = it: reads u_cur = u^{it} and u_prev_next = u^{it-1},
  * overwrites u_prev_next with u^{it+1}, then injects the sources (src may
@@ -257,17 +273,25 @@ void stencil_batch_destroy(stencil_batch *b);
 stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a, void *scratch_b,
                             const stencil_tune_opts *opts, stencil_tune_report *report, void *stream);
 
-/* Current tile of the context (after init, tune or set). */
+/* Current one-step tile of the context (after init, tune or set). */
 stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out);
 
-/* Replace the current tile; rejects tiles this build cannot run on the
- * context's grid (EUNSUPPORTED) without changing the current one. */
+/* Current two-step tile (EUNSUPPORTED if no two-step kernel exists for the
+ * context's radius and storage). */
+stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out);
+
+/* Replace the current tile (a ZMARCH2 tile replaces the two-step tile);
+ * rejects tiles this build cannot run on the context's grid (EUNSUPPORTED)
+ * without changing the current one. */
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
 /* Compiled ZMARCH tiles for a radius and storage type, with vw = 4
  * (vec4 != 0) or 1, dz = 0. Writes at most cap entries to out (out may be
  * NULL) and returns the total count, or a negative stencil_status. */
 int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stencil_tile *out, int32_t cap);
+
+/* Compiled two-step tiles (kind ZMARCH2, dz = 0) for a radius, FP32 storage. */
+int32_t stencil_list_tiles2(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap);
 
 /* Between FP32 wavefields and the context's storage: to_storage != 0 writes
  * dst = round(src * storage_scale) (nearest even) in the storage type;

@@ -35,7 +35,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EUNSUPPORTED, EALIAS = 0, -1, -2, -3, -4, -5, -6
 F32, F16, BF16 = 0, 1, 2
 STORAGES = {"f32": F32, "f16": F16, "bf16": BF16}
-TILE_AUTO, TILE_PLAIN, TILE_ZMARCH = 0, 1, 2
+TILE_AUTO, TILE_PLAIN, TILE_ZMARCH, TILE_ZMARCH2 = 0, 1, 2, 3
 POLICY_WORST, POLICY_MIN, POLICY_AVG, POLICY_OB = 0, 1, 2, 3
 POLICIES = {"worst": POLICY_WORST, "mwmb": POLICY_WORST, "min": POLICY_MIN, "mmmb": POLICY_MIN,
             "avg": POLICY_AVG, "mamb": POLICY_AVG, "ob": POLICY_OB}
@@ -74,7 +74,8 @@ class StencilTuneOpts(ctypes.Structure):
     _fields_ = [("policy", ctypes.c_int32), ("n_iter", ctypes.c_int32), ("n_rep", ctypes.c_int32),
                 ("warmup", ctypes.c_int32), ("parts", ctypes.c_int32), ("include_plain", ctypes.c_int32),
                 ("cache_path", ctypes.c_char_p), ("table", ctypes.POINTER(ctypes.c_double)),
-                ("candidates", ctypes.POINTER(StencilTile)), ("table_cap", ctypes.c_int32)]
+                ("candidates", ctypes.POINTER(StencilTile)), ("table_cap", ctypes.c_int32),
+                ("temporal", ctypes.c_int32), ("scratch_c", ctypes.c_void_p), ("scratch_d", ctypes.c_void_p)]
 
 
 class StencilTuneReport(ctypes.Structure):
@@ -92,6 +93,9 @@ _sig = {
     "stencil_kappa": (_i32, [_vp, _vp, _vp, _vp]),
     "stencil_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
     "stencil_step_to": (_i32, [_vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
+    "stencil_step2": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp]),
+    "stencil_get_tile2": (_i32, [_vp, ctypes.POINTER(StencilTile)]),
+    "stencil_list_tiles2": (_i32, [_i32, _i32, ctypes.POINTER(StencilTile), _i32]),
     "stencil_kappa_slowness2": (_i32, [_vp, _vp, _vp, _vp]),
     "stencil_sample": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "stencil_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp, _vp, _vp, _vp,
@@ -207,6 +211,25 @@ def stencil_step_to(ctx, kappa, u_cur, u_prev, u_next, it=0, src: StencilSrc | N
                                 ctypes.byref(src) if src is not None else None, _stream(stream)), ctx)
 
 
+def stencil_step2(ctx, kappa, u_cur, u_prev, u_next, u_next2, it=0, src: StencilSrc | None = None, stream=None):
+    _check(_lib.stencil_step2(ctx, _ptr(kappa), _ptr(u_cur), _ptr(u_prev), _ptr(u_next), _ptr(u_next2), int(it),
+                              ctypes.byref(src) if src is not None else None, _stream(stream)), ctx)
+
+
+def stencil_get_tile2(ctx) -> StencilTile:
+    t = StencilTile()
+    _check(_lib.stencil_get_tile2(ctx, ctypes.byref(t)), ctx)
+    return t
+
+
+def stencil_list_tiles2(radius: int, vec4: bool = True):
+    n = _lib.stencil_list_tiles2(radius, int(vec4), None, 0)
+    _check(min(n, 0))
+    arr = (StencilTile * max(n, 1))()
+    _lib.stencil_list_tiles2(radius, int(vec4), arr, n)
+    return [arr[i] for i in range(n)]
+
+
 def stencil_kappa_slowness2(ctx, m, kappa, stream=None):
     _check(_lib.stencil_kappa_slowness2(ctx, _ptr(m), _ptr(kappa), _stream(stream)), ctx)
 
@@ -252,7 +275,8 @@ def stencil_batch_tune(shots, policy="worst", n_iter=0, n_rep=0, warmup=0, parts
     """Search one tile for a whole batch; shots as for stencil_batch_create.
     Returns the report dict; every shot's context tile is set to the winner."""
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
-    opts = StencilTuneOpts(pol, n_iter, n_rep, warmup, parts, int(bool(include_plain)), None, None, None, 0)
+    opts = StencilTuneOpts(pol, n_iter, n_rep, warmup, parts, int(bool(include_plain)), None, None, None, 0, 1,
+                           None, None)
     rep = StencilTuneReport()
     _check(_lib.stencil_batch_tune(_shot_array(shots), len(shots), ctypes.byref(opts), ctypes.byref(rep),
                                    _stream(stream)))
@@ -276,7 +300,8 @@ def stencil_batch_destroy(batch):
 
 
 def stencil_tune(ctx, kappa, scratch_a, scratch_b, policy="worst", n_iter=0, n_rep=0, warmup=0, parts=0,
-                 include_plain=False, cache_path=None, table_cap=0, stream=None):
+                 include_plain=False, cache_path=None, table_cap=0, stream=None, temporal=1, scratch_c=None,
+                 scratch_d=None):
     """Run the blocksize search. Returns (report dict, table [n_rep][nC] or None,
     candidates list or None)."""
     pol = POLICIES[policy] if isinstance(policy, str) else int(policy)
@@ -285,7 +310,8 @@ def stencil_tune(ctx, kappa, scratch_a, scratch_b, policy="worst", n_iter=0, n_r
     opts = StencilTuneOpts(pol, n_iter, n_rep, warmup, parts, int(bool(include_plain)),
                            cache_path.encode() if cache_path else None,
                            ctypes.cast(table, ctypes.POINTER(ctypes.c_double)) if table else None,
-                           ctypes.cast(cands, ctypes.POINTER(StencilTile)) if cands else None, table_cap)
+                           ctypes.cast(cands, ctypes.POINTER(StencilTile)) if cands else None, table_cap,
+                           int(temporal), _ptr(scratch_c), _ptr(scratch_d))
     rep = StencilTuneReport()
     _check(_lib.stencil_tune(ctx, _ptr(kappa), _ptr(scratch_a), _ptr(scratch_b), ctypes.byref(opts),
                              ctypes.byref(rep), _stream(stream)), ctx)
@@ -429,6 +455,10 @@ class Propagator:
     def tile(self) -> StencilTile:
         return stencil_get_tile(self.ctx)
 
+    @property
+    def tile2(self) -> StencilTile:
+        return stencil_get_tile2(self.ctx)
+
     @tile.setter
     def tile(self, t: StencilTile):
         stencil_set_tile(self.ctx, t)
@@ -438,15 +468,30 @@ class Propagator:
         self._check_field(u_prev_next)
         stencil_step(self.ctx, self.kappa, u_cur, u_prev_next, it, src, stream)
 
-    def run(self, u_cur, u_prev, nt: int, src: StencilSrc | None = None, it0: int = 0, stream=None):
+    def run(self, u_cur, u_prev, nt: int, src: StencilSrc | None = None, it0: int = 0, stream=None,
+            temporal: int = 1, spare=None):
         """Advance nt steps from (u^{it0}, u^{it0-1}); returns the tensors now
-        holding (u^{it0+nt}, u^{it0+nt-1})."""
+        holding (u^{it0+nt}, u^{it0+nt-1}).
+
+        temporal=2 uses two-step launches (bit-identical results), which need
+        two more wavefield buffers: ``spare`` = (c, d), allocated if None; an
+        odd nt ends with one one-step launch."""
         self._check_field(u_cur)
         self._check_field(u_prev)
         a, b = u_cur, u_prev
-        for it in range(it0, it0 + nt):
+        it = it0
+        if temporal == 2 and nt >= 2:
+            c, d = spare if spare is not None else (self.zeros(), self.zeros())
+            self._check_field(c)
+            self._check_field(d)
+            while it + 2 <= it0 + nt:
+                stencil_step2(self.ctx, self.kappa, a, b, c, d, it, src, stream)
+                a, b, c, d = d, c, b, a
+                it += 2
+        while it < it0 + nt:
             stencil_step(self.ctx, self.kappa, a, b, it, src, stream)
             a, b = b, a
+            it += 1
         return a, b
 
     def tune(self, scratch_a=None, scratch_b=None, **opts):
@@ -454,6 +499,9 @@ class Propagator:
             scratch_a = self.zeros()
         if scratch_b is None:
             scratch_b = self.zeros()
+        if opts.get("temporal", 1) == 2:
+            opts.setdefault("scratch_c", self.zeros())
+            opts.setdefault("scratch_d", self.zeros())
         return stencil_tune(self.ctx, self.kappa, scratch_a, scratch_b, **opts)
 
 

@@ -17,6 +17,7 @@
 #include "internal.h"
 
 using p1310::SweepArgs;
+using p1310::Z2Variant;
 using p1310::ZVariant;
 
 struct stencil_ctx {
@@ -26,7 +27,8 @@ struct stencil_ctx {
     int es = 4;            // bytes per wavefield value
     float scale = 1.0f;    // storage scale (power of two)
     float cf[p1310::kMaxRadius + 1] = {};  // 3*c_0, c_1..c_R in FP32
-    stencil_tile tile = {};
+    stencil_tile tile = {};   // one-step sweeps
+    stencil_tile tile2 = {};  // two-step sweeps (kind STENCIL_TILE_ZMARCH2)
     std::string err;
 };
 
@@ -156,6 +158,15 @@ const ZVariant *find_variant(const stencil_ctx *ctx, const stencil_tile &t)
     return nullptr;
 }
 
+const Z2Variant *find_variant2(const stencil_ctx *ctx, const stencil_tile &t)
+{
+    for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
+        const Z2Variant *v = p1310::zmarch2_variant(i);
+        if (v->R == ctx->R && v->st == ctx->st && v->bx == t.bx && v->by == t.by && v->vw == t.vw) return v;
+    }
+    return nullptr;
+}
+
 // Checks a concrete tile against the grid; on success fills *norm with the
 // normalised tile (vw picked, xcd clamped).
 stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile *norm)
@@ -172,6 +183,23 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
         t.vw = 1;
         t.xcd = 0;
         t.pf = 0;
+        *norm = t;
+        return STENCIL_OK;
+    }
+    if (t.kind == STENCIL_TILE_ZMARCH2) {
+        if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
+        if (t.vw == 4 && !vec4_ok(ctx)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
+        t.ry = 1;
+        t.pf = 0;
+        const Z2Variant *v = find_variant2(ctx, t);
+        if (!v) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled two-step kernel for this (bx, by, vw), radius, storage");
+        if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
+        if (t.dz > d.nz) t.dz = (int32_t)d.nz;
+        if ((t.dz + 4 * ctx->R) * d.nx * d.ny * 4 >= kWindowLimit)
+            return fail(ctx, STENCIL_EUNSUPPORTED, "two-step window (dz + 4R planes) must stay below 2 GiB; lower dz");
+        const int64_t gx = (d.nx + v->own_x - 1) / v->own_x, gy = (d.ny + v->own_y - 1) / v->own_y;
+        if (gx * gy * ((d.nz + t.dz - 1) / t.dz) > 0x7fffffff) return fail(ctx, STENCIL_EUNSUPPORTED, "too many workgroups");
+        t.xcd = t.xcd ? kXcds : 0;
         *norm = t;
         return STENCIL_OK;
     }
@@ -228,12 +256,31 @@ stencil_tile default_tile(const stencil_ctx *ctx)
     return t;
 }
 
+stencil_tile default_tile2(const stencil_ctx *ctx)
+{
+    stencil_tile t = {};
+    t.kind = STENCIL_TILE_ZMARCH2;
+    if (vec4_ok(ctx)) {
+        t.bx = 16;
+        t.by = 32;
+        t.vw = 4;
+    } else {
+        t.bx = 32;
+        t.by = 16;
+        t.vw = 1;
+    }
+    t.ry = 1;
+    t.dz = 64;
+    t.xcd = 1;
+    return t;
+}
+
 // --------------------------------------------------------------------------
 // Tune cache: one line per entry,
 //   gfx950 R<r> f32 <nx> <ny> <nz> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms> <actual_ms>
 // The last matching line wins.
 // --------------------------------------------------------------------------
-bool cache_lookup(const char *path, const stencil_ctx *ctx, stencil_tile *t, double *mn, double *act)
+bool cache_lookup(const char *path, const stencil_ctx *ctx, bool two, stencil_tile *t, double *mn, double *act)
 {
     if (!path || !*path) return false;
     FILE *f = std::fopen(path, "r");
@@ -250,8 +297,10 @@ bool cache_lookup(const char *path, const stencil_ctx *ctx, stencil_tile *t, dou
         if (n != 16) continue;
         char want[8];
         std::snprintf(want, sizeof want, "R%d", ctx->R);
-        if (std::strcmp(arch, "gfx950") || std::strcmp(rr, want) || std::strcmp(dt, "f32")) continue;
+        static const char *kst[] = {"f32", "f16", "bf16"};
+        if (std::strcmp(arch, "gfx950") || std::strcmp(rr, want) || std::strcmp(dt, kst[ctx->st])) continue;
         if (nx != ctx->d.nx || ny != ctx->d.ny || nz != ctx->d.nz) continue;
+        if ((c.kind == STENCIL_TILE_ZMARCH2) != two) continue;
         *t = c;
         *mn = a;
         *act = b;
@@ -266,7 +315,8 @@ void cache_store(const char *path, const stencil_ctx *ctx, const stencil_tile &t
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "gfx950 R%d f32 %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", ctx->R,
+    static const char *kst[] = {"f32", "f16", "bf16"};
+    std::fprintf(f, "gfx950 R%d %s %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", ctx->R, kst[ctx->st],
                  (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, t.kind, t.bx, t.by, t.ry, t.dz,
                  t.vw, t.xcd, t.pf, mn, act);
     std::fclose(f);
@@ -380,6 +430,22 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
     std::vector<stencil_tile> out;
     const stencil_desc &d = ctx->d;
     const int vw = vec4_ok(ctx) ? 4 : 1;
+    if (o.temporal == 2) {
+        // Two-step shapes x march depths x XCD order.
+        const int64_t dzs[] = {16, 32, 64, 128, 256, d.nz};
+        for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
+            const Z2Variant *v = p1310::zmarch2_variant(i);
+            if (v->R != ctx->R || v->st != ctx->st || v->vw != vw) continue;
+            for (int64_t dz : dzs) {
+                if (dz > d.nz) continue;
+                for (int xcd = 1; xcd >= 0; --xcd) {
+                    stencil_tile t = {STENCIL_TILE_ZMARCH2, v->bx, v->by, 1, (int32_t)dz, v->vw, xcd, 0};
+                    push_unique(ctx, out, t);
+                }
+            }
+        }
+        return out;
+    }
     std::vector<const ZVariant *> vars;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
@@ -468,6 +534,80 @@ double time_tile(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, vo
     return ms;
 }
 
+// Enqueue one two-step launch (u^{it+1} and u^{it+2}) with a checked tile.
+hipError_t enqueue_step2(const stencil_ctx *ctx, const stencil_tile &t, const float *kappa, const void *ucur,
+                         const void *uprev, void *unext, void *unext2, int64_t it, const stencil_src *src,
+                         hipStream_t s)
+{
+    const stencil_desc &d = ctx->d;
+    const Z2Variant *v = find_variant2(ctx, t);
+    if (!v) return hipErrorInvalidValue;
+    SweepArgs a = {};
+    a.kappa = kappa;
+    a.ucur = ucur;
+    a.uprev = uprev;
+    a.unext = unext;
+    a.unext2 = unext2;
+    a.nx = (int)d.nx;
+    a.ny = (int)d.ny;
+    a.nz = (int)d.nz;
+    for (int m = 0; m <= ctx->R; ++m) a.c[m] = ctx->cf[m];
+    a.scale = ctx->scale;
+    a.nsrc = (src && src->n == 1) ? 1 : 0;
+    a.src_idx = a.nsrc ? src->idx : nullptr;
+    a.src_amp = a.nsrc ? src->amp : nullptr;
+    a.it = it;
+    a.dz = t.dz;
+    a.gx = (int)((d.nx + v->own_x - 1) / v->own_x);
+    a.gy = (int)((d.ny + v->own_y - 1) / v->own_y);
+    a.gz = (int)((d.nz + t.dz - 1) / t.dz);
+    a.xcd = t.xcd;
+    return p1310::launch_zmarch2(*v, a, s);
+}
+
+// Time `steps` steps (steps/2 two-step launches, steps even) of a two-step
+// tile over four scratch fields; +inf if a launch failed.
+double time_tile2(stencil_ctx *ctx, const stencil_tile &t, const float *kappa, void *f[4], int warm, int steps,
+                  hipStream_t s, hipEvent_t e0, hipEvent_t e1, hipError_t *err)
+{
+    auto launch = [&]() -> hipError_t {
+        hipError_t e = enqueue_step2(ctx, t, kappa, f[0], f[1], f[2], f[3], 0, nullptr, s);
+        // (u^{n+2}, u^{n+1}) become the inputs; the old inputs are free.
+        void *cur = f[0], *prev = f[1];
+        f[0] = f[3];
+        f[1] = f[2];
+        f[2] = prev;
+        f[3] = cur;
+        return e;
+    };
+    for (int i = 0; i < (warm + 1) / 2; ++i) {
+        hipError_t e = launch();
+        if (e != hipSuccess) {
+            *err = e;
+            return std::numeric_limits<double>::infinity();
+        }
+    }
+    hipEventRecord(e0, s);
+    for (int i = 0; i < steps / 2; ++i) {
+        hipError_t e = launch();
+        if (e != hipSuccess) {
+            *err = e;
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            return std::numeric_limits<double>::infinity();
+        }
+    }
+    hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e != hipSuccess) {
+        *err = e;
+        return std::numeric_limits<double>::infinity();
+    }
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,7 +675,7 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     } else {
         double mn, act;
         stencil_tile c;
-        if (cache_lookup(std::getenv("STENCIL_TUNE_CACHE"), ctx, &c, &mn, &act)) t = c;
+        if (cache_lookup(std::getenv("STENCIL_TUNE_CACHE"), ctx, false, &c, &mn, &act)) t = c;
     }
     stencil_tile norm;
     stencil_status st = check_tile(ctx, t, &norm);
@@ -546,6 +686,8 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
         return st;
     }
     ctx->tile = norm;
+    if (check_tile(ctx, default_tile2(ctx), &norm) == STENCIL_OK) ctx->tile2 = norm;
+    ctx->err.clear();
     *out = ctx;
     return STENCIL_OK;
 }
@@ -567,7 +709,68 @@ stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile)
     if (t.kind == STENCIL_TILE_AUTO) t = default_tile(ctx);
     stencil_status st = check_tile(ctx, t, &norm);
     if (st != STENCIL_OK) return st;
-    ctx->tile = norm;
+    if (norm.kind == STENCIL_TILE_ZMARCH2) ctx->tile2 = norm;
+    else ctx->tile = norm;
+    return STENCIL_OK;
+}
+
+stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out)
+{
+    if (!ctx || !out) return STENCIL_EINVAL;
+    if (ctx->tile2.kind != STENCIL_TILE_ZMARCH2) return STENCIL_EUNSUPPORTED;
+    *out = ctx->tile2;
+    return STENCIL_OK;
+}
+
+int32_t stencil_list_tiles2(int32_t radius, int32_t vec4, stencil_tile *out, int32_t cap)
+{
+    if (!radius_ok(radius) || cap < 0) return STENCIL_EINVAL;
+    int32_t n = 0;
+    for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
+        const Z2Variant *v = p1310::zmarch2_variant(i);
+        if (v->R != radius || v->vw != (vec4 ? 4 : 1)) continue;
+        if (out && n < cap) {
+            stencil_tile t = {};
+            t.kind = STENCIL_TILE_ZMARCH2;
+            t.bx = v->bx;
+            t.by = v->by;
+            t.ry = 1;
+            t.vw = v->vw;
+            out[n] = t;
+        }
+        ++n;
+    }
+    return n;
+}
+
+stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
+                             void *u_next, void *u_next2, int64_t it, const stencil_src *src, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!kappa || !u_cur || !u_prev || !u_next || !u_next2) return fail(ctx, STENCIL_EINVAL, "null field pointer");
+    if (ctx->tile2.kind != STENCIL_TILE_ZMARCH2)
+        return fail(ctx, STENCIL_EUNSUPPORTED, "no two-step kernel for this radius and storage");
+    const int64_t ub = npoints(ctx) * ctx->es, kb = npoints(ctx) * 4;
+    const void *f[] = {u_cur, u_prev, u_next, u_next2};
+    for (int i = 0; i < 4; ++i) {
+        if (overlaps2(kappa, kb, f[i], ub)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps a wavefield");
+        for (int j = i + 1; j < 4; ++j)
+            if (overlaps(f[i], f[j], ub)) return fail(ctx, STENCIL_EALIAS, "the four wavefields must not overlap");
+    }
+    if (ctx->tile2.vw == 4 &&
+        (((uintptr_t)kappa & 15u) || (((uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next |
+                                       (uintptr_t)u_next2) & (uintptr_t)(4 * ctx->es - 1))))
+        return fail(ctx, STENCIL_EINVAL, "kappa must be 16-byte and the wavefields 4-value aligned for vw = 4");
+    if (src && src->n != 0) {
+        if (src->n > 1) return fail(ctx, STENCIL_EUNSUPPORTED, "two-step launches take at most one source");
+        if (!src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
+        if (it < 0 || it + 1 >= src->nt) return fail(ctx, STENCIL_EINVAL, "steps it and it+1 need source samples");
+    }
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = enqueue_step2(ctx, ctx->tile2, (const float *)kappa, u_cur, u_prev, u_next, u_next2, it,
+                                 (src && src->n) ? src : nullptr, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "two-step sweep launch");
     return STENCIL_OK;
 }
 
@@ -727,9 +930,25 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     stencil_tune_opts o = {};
     if (opts) o = *opts;
     if (o.policy < STENCIL_POLICY_WORST || o.policy > STENCIL_POLICY_OB) return fail(ctx, STENCIL_EINVAL, "bad policy");
-    if (o.n_iter < 0 || o.n_rep < 0 || o.parts < 0 || o.parts == 1 || o.table_cap < 0)
+    if (o.n_iter < 0 || o.n_rep < 0 || o.parts < 0 || o.parts == 1 || o.table_cap < 0 ||
+        (o.temporal != 0 && o.temporal != 1 && o.temporal != 2))
         return fail(ctx, STENCIL_EINVAL, "bad tune options");
-    const int n_iter = o.n_iter ? o.n_iter : 10;
+    const bool two = o.temporal == 2;
+    if (two) {
+        if (ctx->tile2.kind != STENCIL_TILE_ZMARCH2)
+            return fail(ctx, STENCIL_EUNSUPPORTED, "no two-step kernel for this radius and storage");
+        if (!o.scratch_c || !o.scratch_d) return fail(ctx, STENCIL_EINVAL, "two-step search needs scratch_c and scratch_d");
+        const void *f[] = {scratch_a, scratch_b, o.scratch_c, o.scratch_d};
+        for (int i = 0; i < 4; ++i) {
+            if (overlaps2(kappa, kbytes, f[i], bytes) || (((uintptr_t)f[i]) & 15u))
+                return fail(ctx, overlaps2(kappa, kbytes, f[i], bytes) ? STENCIL_EALIAS : STENCIL_EINVAL,
+                            "bad scratch field");
+            for (int j = i + 1; j < 4; ++j)
+                if (overlaps(f[i], f[j], bytes)) return fail(ctx, STENCIL_EALIAS, "scratch fields overlap");
+        }
+    }
+    int n_iter = o.n_iter ? o.n_iter : 10;
+    if (two && (n_iter & 1)) ++n_iter;
     const int n_rep = o.n_rep ? o.n_rep : 3;
     const int warm = o.warmup == 0 ? 2 : (o.warmup < 0 ? 0 : o.warmup);
     *report = stencil_tune_report{};
@@ -738,10 +957,11 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     {
         stencil_tile c;
         double mn, act;
-        if (cache_lookup(o.cache_path, ctx, &c, &mn, &act)) {
+        if (cache_lookup(o.cache_path, ctx, two, &c, &mn, &act)) {
             stencil_tile norm;
             if (check_tile(ctx, c, &norm) == STENCIL_OK) {
-                ctx->tile = norm;
+                if (two) ctx->tile2 = norm;
+                else ctx->tile = norm;
                 report->tile = norm;
                 report->min_time_ms = mn;
                 report->actual_time_ms = act;
@@ -768,7 +988,12 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
         return hip_fail(ctx, he, "hipEventCreate");
     }
     void *a = scratch_a, *b = scratch_b;
+    void *f4[4] = {scratch_a, scratch_b, o.scratch_c, o.scratch_d};
     const float *k = (const float *)kappa;
+    auto time_any = [&](const stencil_tile &t, hipError_t *e) {
+        return two ? time_tile2(ctx, t, k, f4, warm, n_iter, s, e0, e1, e)
+                   : time_tile(ctx, t, k, a, b, warm, n_iter, s, e0, e1, e);
+    };
     std::vector<double> table((size_t)n_rep * nC, std::numeric_limits<double>::infinity());
     hipError_t last = hipSuccess;
 
@@ -776,7 +1001,7 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     for (int r = 0; r < n_rep; ++r)
         for (int c = 0; c < nC; ++c) {
             hipError_t e = hipSuccess;
-            table[(size_t)r * nC + c] = time_tile(ctx, cands[c], k, a, b, warm, n_iter, s, e0, e1, &e);
+            table[(size_t)r * nC + c] = time_any(cands[c], &e);
             if (e != hipSuccess) last = e;
         }
     bool any = false;
@@ -792,16 +1017,16 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
 
     // Verification phase: the chosen tile again, then the default for context.
     hipError_t e = hipSuccess;
-    const double actual = time_tile(ctx, cands[best], k, a, b, warm, n_iter, s, e0, e1, &e);
+    const double actual = time_any(cands[best], &e);
     stencil_tile dflt;
     double dtime = std::numeric_limits<double>::infinity();
-    if (check_tile(ctx, default_tile(ctx), &dflt) == STENCIL_OK)
-        dtime = time_tile(ctx, dflt, k, a, b, warm, n_iter, s, e0, e1, &e);
+    if (check_tile(ctx, two ? default_tile2(ctx) : default_tile(ctx), &dflt) == STENCIL_OK) dtime = time_any(dflt, &e);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (!std::isfinite(actual)) return hip_fail(ctx, e, "verification run failed");
 
-    ctx->tile = cands[best];
+    if (two) ctx->tile2 = cands[best];
+    else ctx->tile = cands[best];
     report->tile = cands[best];
     report->min_time_ms = min_time;
     report->actual_time_ms = actual;

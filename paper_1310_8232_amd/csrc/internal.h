@@ -16,6 +16,7 @@ struct SweepArgs {
     const void *ucur;        // u^n (storage type of the variant)
     const void *uprev;       // u^{n-1}
     void *unext;             // u^{n+1} (may be uprev: in-place update)
+    void *unext2;            // u^{n+2} (two-step kernels only)
     int nx, ny, nz;
     int dz;                  // planes per workgroup (z-march)
     int gx, gy, gz;          // tiles along x, y and z-chunks
@@ -43,6 +44,19 @@ struct ZVariant {
 // Registry of compiled z-march kernels (kernels.hip).
 int zmarch_variant_count();
 const ZVariant *zmarch_variant(int i);
+
+// One compiled two-step (temporally blocked) z-march instantiation: a
+// workgroup of bx x by threads covers an extended tile of (bx*vw) x by points,
+// its own tile is (bx*vw - 2*hx) x (by - 2R).
+struct Z2Variant {
+    int R, bx, by, vw, st;
+    void (*kernel)(SweepArgs);
+    int threads;
+    int own_x, own_y;
+};
+int zmarch2_variant_count();
+const Z2Variant *zmarch2_variant(int i);
+hipError_t launch_zmarch2(const Z2Variant &v, const SweepArgs &a, hipStream_t s);
 
 // Launchers (kernels.hip). All enqueue on `s` and return the launch status.
 hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s);

@@ -7,6 +7,9 @@ namespace p1310 {
 const ZVariant *zmarch_table_r3(int *n);
 const ZVariant *zmarch_table_r4(int *n);
 const ZVariant *zmarch_table_r5(int *n);
+const Z2Variant *zmarch2_table_r3(int *n);
+const Z2Variant *zmarch2_table_r4(int *n);
+const Z2Variant *zmarch2_table_r5(int *n);
 hipError_t launch_plain_r3(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
 hipError_t launch_plain_r4(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
 hipError_t launch_plain_r5(int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
@@ -30,6 +33,26 @@ struct Registry {
 const Registry &registry()
 {
     static Registry r;
+    return r;
+}
+
+struct Registry2 {
+    const Z2Variant *items[64];
+    int n = 0;
+    Registry2()
+    {
+        const Z2Variant *(*tables[])(int *) = {zmarch2_table_r3, zmarch2_table_r4, zmarch2_table_r5};
+        for (auto f : tables) {
+            int k = 0;
+            const Z2Variant *t = f(&k);
+            for (int i = 0; i < k && n < 64; ++i) items[n++] = &t[i];
+        }
+    }
+};
+
+const Registry2 &registry2()
+{
+    static Registry2 r;
     return r;
 }
 
@@ -216,6 +239,21 @@ const ZVariant *zmarch_variant(int i)
 {
     const Registry &r = registry();
     return (i >= 0 && i < r.n) ? r.items[i] : nullptr;
+}
+
+int zmarch2_variant_count() { return registry2().n; }
+
+const Z2Variant *zmarch2_variant(int i)
+{
+    const Registry2 &r = registry2();
+    return (i >= 0 && i < r.n) ? r.items[i] : nullptr;
+}
+
+hipError_t launch_zmarch2(const Z2Variant &v, const SweepArgs &a, hipStream_t s)
+{
+    const int blocks = a.gx * a.gy * a.gz;
+    hipLaunchKernelGGL(v.kernel, dim3(blocks), dim3(v.threads), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s)

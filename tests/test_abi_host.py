@@ -177,3 +177,41 @@ def test_stream_probe_validation():
         p.stencil_stream_probe(1 << 40, None, None, (1 << 40) + 4096, 102, stream=0)
     with pytest.raises(p.StencilError):
         p.stencil_stream_probe(1 << 40, None, (1 << 40) + 8192, (1 << 40) + 4096, 4096, stream=0)
+
+
+def test_two_step_tile_and_validation():
+    ctx = _init(nx=64, ny=48, nz=40)
+    t2 = p.stencil_get_tile2(ctx)
+    assert t2.kind == p.TILE_ZMARCH2 and t2.vw == 4 and t2.ry == 1
+    tiles = p.stencil_list_tiles2(4, True)
+    assert len(tiles) >= 3
+    for tt in tiles:
+        tt.dz = 8
+        p.stencil_set_tile(ctx, tt)
+        g = p.stencil_get_tile2(ctx)
+        assert (g.bx, g.by, g.dz) == (tt.bx, tt.by, 8)
+    assert p.stencil_get_tile(ctx).kind == p.TILE_ZMARCH  # the one-step tile is unchanged
+    n = 64 * 48 * 40 * 4
+    base = 1 << 40
+    k, a, b, c, d = (base + i * 2 * n for i in range(5))
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step2(ctx, k, a, b, a + 64, d, 0, None, 0)  # output overlaps an input
+    assert e.value.status == p.EALIAS
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step2(ctx, k, a, b, c, c, 0, None, 0)       # both outputs the same buffer
+    assert e.value.status == p.EALIAS
+    src3 = p.StencilSrc(3, base + 64 * n, base + 65 * n, 10)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step2(ctx, k, a, b, c, d, 0, src3, 0)
+    assert e.value.status == p.EUNSUPPORTED
+    src1 = p.StencilSrc(1, base + 64 * n, base + 65 * n, 10)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step2(ctx, k, a, b, c, d, 9, src1, 0)        # step it+1 = 10 has no sample
+    assert e.value.status == p.EINVAL
+    p.stencil_destroy(ctx)
+    # No two-step kernels for 16-bit storage: the context reports it.
+    ctx = _init(storage="f16")
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_get_tile2(ctx)
+    assert e.value.status == p.EUNSUPPORTED
+    p.stencil_destroy(ctx)

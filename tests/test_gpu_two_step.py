@@ -1,0 +1,96 @@
+"""Two leapfrog steps per launch (blocking in time) against one-step
+launches: every two-step tile must give the bits of the one-step path (which
+the parity tests tie to the FP64 oracle), and the 512^3 run is also checked
+against the oracle directly."""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1310_8232_amd as p
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def cuda(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=dtype)
+
+
+def _case(shape, seed, R, nt):
+    nx, ny, nz = shape
+    v = workloads.layered_model(nx, ny, nz, seed=seed)
+    dt, vmax = workloads.dt_for_courant(v, 10.0)
+    u0 = workloads.random_field(nx, ny, nz, seed + 1)
+    um1 = workloads.random_field(nx, ny, nz, seed + 2)
+    idx = np.array([workloads.centre_index(nx, ny, nz)], np.int64)
+    amp = workloads.ricker(nt, dt, 25.0).reshape(-1, 1)
+    return v, dt, vmax, u0, um1, idx, amp
+
+
+def _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal, tile2=None):
+    prop = p.Propagator(cuda(v), 10.0, dt, R, vmax=vmax)
+    if tile2 is not None:
+        prop.tile = tile2
+    keep = (cuda(idx, torch.int64), cuda(amp))
+    src = p.make_src(*keep)
+    a, b = prop.run(cuda(u0), cuda(um1), nt, src, temporal=temporal)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), b.cpu().numpy()
+
+
+@pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (3, (72, 45, 37)), (5, (72, 45, 37)), (4, (61, 29, 23)),
+                                     (4, (260, 67, 19)), (5, (61, 29, 23)), (4, (12, 10, 6)), (4, (1, 1, 1)),
+                                     (4, (8, 40, 3))])
+def test_two_step_bits_equal_one_step(R, shape):
+    nt = 7  # three two-step launches and one closing one-step launch
+    v, dt, vmax, u0, um1, idx, amp = _case(shape, 50 + R, R, nt)
+    log(f"case: two-step vs one-step, R={R} {shape}, {nt} steps")
+    ref = _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal=1)
+    nz = shape[2]
+    tiles = []
+    for t in p.stencil_list_tiles2(R, shape[0] % 4 == 0):
+        for dz in (1, 7, 16, nz):
+            for xcd in (1, 0):
+                tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, 1, dz, t.vw, xcd, 0))
+    assert tiles
+    for t in tiles:
+        got = _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal=2, tile2=t)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), f"tile {t}"
+    log(f"  {len(tiles)} two-step tiles bit-identical to one-step")
+
+
+def test_two_step_search_and_512_against_oracle():
+    nx = ny = nz = 512
+    log("case: 512^3 layered kappa, random fields, source, 4 steps: searched two-step tile vs oracle and one-step")
+    t0 = time.time()
+    v, dt, vmax, u0, um1, idx, amp = _case((nx, ny, nz), workloads.SEED, 4, 4)
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    rep, _, _ = prop.tune(temporal=2, n_iter=4, n_rep=2)
+    log(f"  searched {rep['n_candidates']} two-step tiles -> {rep['tile']} gap {rep['gap']:+.4f} ({rep['seconds']:.1f}s)")
+    assert rep["tile"]["kind"] == p.TILE_ZMARCH2 and prop.tile2.as_dict() == rep["tile"]
+    tile2 = prop.tile2
+    del prop
+    torch.cuda.empty_cache()
+    two = _run(v, dt, vmax, 4, u0, um1, idx, amp, 4, temporal=2, tile2=tile2)
+    one = _run(v, dt, vmax, 4, u0, um1, idx, amp, 4, temporal=1)
+    assert np.array_equal(two[0], one[0]) and np.array_equal(two[1], one[1])
+    kap = oracle.kappa(v, dt, 10.0)
+    ref_n, ref_nm1 = oracle.leapfrog(kap, u0, um1, 4, 4, src_idx=idx, amp=amp)
+    e1, e2 = oracle.rel_l2(two[0], ref_n), oracle.rel_l2(two[1], ref_nm1)
+    log(f"  rel_l2 u^4 {e1:.3e} u^3 {e2:.3e} ({time.time() - t0:.1f}s)")
+    assert e1 <= 1e-5 and e2 <= 1e-5
