@@ -57,16 +57,26 @@ def load_traffic(tile: dict, n_points: int):
     return entry.get("hbm_bytes_per_launch")
 
 
-def time_steps(prop, a, b, nsteps, it0, src, stream, temporal=1, spare=None):
+def time_steps(prop, a, b, nsteps, it0, src, stream, temporal=1, spare=None, nseg=1):
+    """Time nsteps steps with HIP events on `stream`; with nseg > 1 the steps
+    run in nseg equal segments with an event between segments (no host
+    synchronisation inside the timed region). Returns (total ms, a, b) or,
+    with nseg > 1, (total ms, a, b, per-segment ms)."""
     import torch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    if nseg < 1 or nsteps % (nseg * temporal):
+        nseg = 1
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
-    a, b = prop.run(a, b, nsteps, src, it0=it0, stream=stream, temporal=temporal, spare=spare)
-    e1.record(stream)
+    ev[0].record(stream)
+    per = nsteps // nseg
+    for k in range(nseg):
+        a, b = prop.run(a, b, per, src, it0=it0 + k * per, stream=stream, temporal=temporal, spare=spare)
+        ev[k + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1), a, b
+    total = ev[0].elapsed_time(ev[nseg])
+    if nseg == 1:
+        return total, a, b
+    return total, a, b, [ev[k].elapsed_time(ev[k + 1]) for k in range(nseg)]
 
 
 def cpu_baseline(cfg, budget_s: float):
@@ -92,9 +102,9 @@ def cpu_baseline(cfg, budget_s: float):
                       f"layered workload from rest (source on), {t1 + t2:.1f} s"}
 
 
-def stream_probe(mib: int, n_in: int, steps: int, warmup: int) -> int:
-    """Time the library's streaming reference: n_in inputs of mib MiB read and
-    one of mib MiB written per launch (n_in = 3 is the sweep's traffic mix)."""
+def stream_rate(mib: int, n_in: int, steps: int, warmup: int):
+    """(ms per launch, GB/s) of the library's streaming reference: n_in inputs
+    of mib MiB read and one of mib MiB written per launch."""
     import torch
 
     import paper_1310_8232_amd as p
@@ -112,10 +122,16 @@ def stream_probe(mib: int, n_in: int, steps: int, warmup: int) -> int:
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    moved = (n_in + 1) * nbytes
+    return ms, (n_in + 1) * nbytes / (ms * 1e-3) / 1e9
+
+
+def stream_probe(mib: int, n_in: int, steps: int, warmup: int) -> int:
+    """Print the streaming reference's rate (n_in = 3 is the sweep's traffic mix)."""
+    nbytes = mib << 20
+    ms, gbs = stream_rate(mib, n_in, steps, warmup)
     print(json.dumps({"stream_probe": {"inputs": n_in, "bytes_read": n_in * nbytes, "bytes_written": nbytes,
                                        "launches": steps, "ms_per_launch": round(ms, 5),
-                                       "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}}), flush=True)
+                                       "gbs": round(gbs, 1)}}), flush=True)
     return 0
 
 
@@ -501,10 +517,15 @@ def main(argv=None):
         b.zero_()
 
     # Warm-up, then exactly `steps` timed steps of the time loop.
-    spare = (torch.zeros_like(prop.kappa), torch.zeros_like(prop.kappa)) if temporal == 2 else None
+    spare = [torch.zeros_like(prop.kappa), torch.zeros_like(prop.kappa)] if temporal == 2 else None
     a, b = prop.run(a, b, args.warmup, src, it0=0, stream=stream, temporal=temporal, spare=spare)
     torch.cuda.synchronize()
-    ms, a, b = time_steps(prop, a, b, args.steps, args.warmup, src, stream, temporal=temporal, spare=spare)
+    res = time_steps(prop, a, b, args.steps, args.warmup, src, stream, temporal=temporal, spare=spare, nseg=5)
+    ms, a, b = res[:3]
+    seg = None
+    if len(res) == 4:
+        g = sorted(npts * (args.steps // 5) / (t * 1e-3) / 1e9 for t in res[3])
+        seg = {"segments": 5, "gpts_min": round(g[0], 3), "gpts_median": round(g[2], 3), "gpts_max": round(g[-1], 3)}
     if not bool(torch.isfinite(a).all()):
         print("bench: non-finite wavefield", file=sys.stderr)
         return 1
@@ -517,23 +538,29 @@ def main(argv=None):
     launch_bytes = (BYTES_PER_UPDATE if temporal == 1 else 20) * npts
     achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
     traffic = load_traffic(tile, npts)
+    # Streaming reference with the one-step sweep's traffic mix (three 512 MiB
+    # inputs, one output), timed after the sweep: the practical HBM ceiling.
+    del a, b, spare
+    s_ms, s_gbs = stream_rate(512, 3, 20, 3)
+    ceiling = {"stream_3in_1out_gbs": round(s_gbs, 1),
+               "sweep_frac_of_stream": round(npts * 16 / (step_ms * 1e-3) / 1e9 / s_gbs, 4)}
     out = {
         "metric": METRIC, "value": round(gpts, 3), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{cfg['name']} layered model, 8th order (R={args.radius}) 25-point star, "
+        "config": {"workload": f"{cfg['name']} layered model, order {2 * args.radius} (R={args.radius}) {6 * args.radius + 1}-point star, "
                                f"FP32, Ricker source, {args.steps} timed steps",
                    "grid": [n, n, n], "radius": args.radius, "tile": tile, "tune": tune,
                    "plain_tiling": compare.get("plain_tiling"), "default_tile": compare.get("default_tile"),
                    "speedup_vs_plain": (round(gpts / compare["plain_tiling"]["gpts"], 3)
-                                        if "plain_tiling" in compare else None)},
+                                        if "plain_tiling" in compare else None),
+                   "timed_segments": seg, "stream_ceiling": ceiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic if temporal == 1 else None},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        del a, b
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
     print(json.dumps(out), flush=True)
     return 0

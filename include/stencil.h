@@ -79,7 +79,7 @@ typedef struct {
     int32_t dz;     /* planes per workgroup along z (ZMARCH); threads along z (PLAIN) */
     int32_t vw;     /* x points per thread: 4 (needs nx % 4 == 0) or 1; 0 = pick */
     int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
-    int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH) */
+    int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2) */
 } stencil_tile;
 
 typedef struct {

@@ -475,7 +475,9 @@ class Propagator:
 
         temporal=2 uses two-step launches (bit-identical results), which need
         two more wavefield buffers: ``spare`` = (c, d), allocated if None; an
-        odd nt ends with one one-step launch."""
+        odd nt ends with one one-step launch. The four buffers rotate, so the
+        returned pair may be two of the spares; pass ``spare`` as a list to
+        get back, in place, the two buffers that are free afterwards."""
         self._check_field(u_cur)
         self._check_field(u_prev)
         a, b = u_cur, u_prev
@@ -488,6 +490,8 @@ class Propagator:
                 stencil_step2(self.ctx, self.kappa, a, b, c, d, it, src, stream)
                 a, b, c, d = d, c, b, a
                 it += 2
+            if isinstance(spare, list):
+                spare[:] = [c, d]
         while it < it0 + nt:
             stencil_step(self.ctx, self.kappa, a, b, it, src, stream)
             a, b = b, a

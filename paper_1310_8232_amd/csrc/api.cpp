@@ -162,7 +162,9 @@ const Z2Variant *find_variant2(const stencil_ctx *ctx, const stencil_tile &t)
 {
     for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
         const Z2Variant *v = p1310::zmarch2_variant(i);
-        if (v->R == ctx->R && v->st == ctx->st && v->bx == t.bx && v->by == t.by && v->vw == t.vw) return v;
+        if (v->R == ctx->R && v->st == ctx->st && v->bx == t.bx && v->by == t.by && v->vw == t.vw &&
+            v->pf == t.pf)
+            return v;
     }
     return nullptr;
 }
@@ -190,7 +192,6 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
         if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
         if (t.vw == 4 && !vec4_ok(ctx)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
         t.ry = 1;
-        t.pf = 0;
         const Z2Variant *v = find_variant2(ctx, t);
         if (!v) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled two-step kernel for this (bx, by, vw), radius, storage");
         if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
@@ -261,8 +262,8 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
     stencil_tile t = {};
     t.kind = STENCIL_TILE_ZMARCH2;
     if (vec4_ok(ctx)) {
-        t.bx = 16;
-        t.by = 32;
+        t.bx = 18;
+        t.by = 40;
         t.vw = 4;
     } else {
         t.bx = 32;
@@ -270,7 +271,7 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
         t.vw = 1;
     }
     t.ry = 1;
-    t.dz = 64;
+    t.dz = 128;
     t.xcd = 1;
     return t;
 }
@@ -439,7 +440,7 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
             for (int64_t dz : dzs) {
                 if (dz > d.nz) continue;
                 for (int xcd = 1; xcd >= 0; --xcd) {
-                    stencil_tile t = {STENCIL_TILE_ZMARCH2, v->bx, v->by, 1, (int32_t)dz, v->vw, xcd, 0};
+                    stencil_tile t = {STENCIL_TILE_ZMARCH2, v->bx, v->by, 1, (int32_t)dz, v->vw, xcd, v->pf};
                     push_unique(ctx, out, t);
                 }
             }
@@ -736,6 +737,7 @@ int32_t stencil_list_tiles2(int32_t radius, int32_t vec4, stencil_tile *out, int
             t.by = v->by;
             t.ry = 1;
             t.vw = v->vw;
+            t.pf = v->pf;
             out[n] = t;
         }
         ++n;

@@ -49,7 +49,7 @@ const ZVariant *zmarch_variant(int i);
 // workgroup of bx x by threads covers an extended tile of (bx*vw) x by points,
 // its own tile is (bx*vw - 2*hx) x (by - 2R).
 struct Z2Variant {
-    int R, bx, by, vw, st;
+    int R, bx, by, vw, pf, st;
     void (*kernel)(SweepArgs);
     int threads;
     int own_x, own_y;

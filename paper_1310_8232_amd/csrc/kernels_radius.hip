@@ -51,13 +51,14 @@ static const ZVariant kTable[] = {
     ZV16(kF16) ZV16(kBF16)
 };
 
-// Two-step kernels (RY = 1, FP32 storage): (BX, BY, VW).
-#define Z2V(BX, BY, VW)                                                                           \
-    {RADIUS, BX, BY, VW, kF32, zmarch2_kernel<RADIUS, BX, BY, VW, float>, BX * BY,               \
+// Two-step kernels (RY = 1, FP32 storage): (BX, BY, VW, PF).
+#define Z2V(BX, BY, VW, PF)                                                                       \
+    {RADIUS, BX, BY, VW, PF, kF32, zmarch2_kernel<RADIUS, BX, BY, VW, PF, float>, BX * BY,       \
      BX * VW - 2 * ((VW == 1) ? RADIUS : ((RADIUS + VW - 1) / VW) * VW), BY - 2 * RADIUS},
 
 static const Z2Variant kTable2[] = {
-    Z2V(16, 32, 4) Z2V(8, 64, 4) Z2V(32, 16, 4) Z2V(16, 16, 4) Z2V(32, 16, 1)
+    Z2V(16, 32, 4, 0) Z2V(16, 32, 4, 1) Z2V(18, 40, 4, 0) Z2V(18, 32, 4, 0) Z2V(16, 24, 4, 0)
+    Z2V(8, 64, 4, 1) Z2V(32, 16, 1, 0)
 };
 
 const Z2Variant *P1310_CAT(zmarch2_table_r, RADIUS)(int *n)

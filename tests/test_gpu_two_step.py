@@ -66,7 +66,7 @@ def test_two_step_bits_equal_one_step(R, shape):
     for t in p.stencil_list_tiles2(R, shape[0] % 4 == 0):
         for dz in (1, 7, 16, nz):
             for xcd in (1, 0):
-                tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, 1, dz, t.vw, xcd, 0))
+                tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, 1, dz, t.vw, xcd, t.pf))
     assert tiles
     for t in tiles:
         got = _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal=2, tile2=t)
@@ -94,3 +94,25 @@ def test_two_step_search_and_512_against_oracle():
     e1, e2 = oracle.rel_l2(two[0], ref_n), oracle.rel_l2(two[1], ref_nm1)
     log(f"  rel_l2 u^4 {e1:.3e} u^3 {e2:.3e} ({time.time() - t0:.1f}s)")
     assert e1 <= 1e-5 and e2 <= 1e-5
+
+
+def test_run_in_segments_with_spare_list():
+    # Two-step runs resumed segment after segment with the spare buffers
+    # handed back in place: odd and even segment lengths, a graph-free loop
+    # like the bench's timed segments. Equal to one-step launches bit for bit.
+    shape, R = (72, 45, 37), 4
+    v, dt, vmax, u0, um1, idx, amp = _case(shape, 91, R, 40)
+    log(f"case: two-step runs in segments 6, 5, 10, 1, 8 with a spare list, {shape}")
+    prop = p.Propagator(cuda(v), 10.0, dt, R, vmax=vmax)
+    src = p.make_src(cuda(idx, torch.int64), cuda(amp))
+    a, b = cuda(u0), cuda(um1)
+    spare = [prop.zeros(), prop.zeros()]
+    it = 0
+    for n in (6, 5, 10, 1, 8):
+        a, b = prop.run(a, b, n, src, it0=it, temporal=2, spare=spare)
+        it += n
+        ptrs = {t.data_ptr() for t in (a, b, *spare)}
+        assert len(ptrs) == 4  # the pair and the spares never alias
+    ra, rb = prop.run(cuda(u0), cuda(um1), it, src, temporal=1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, ra) and torch.equal(b, rb)
