@@ -416,7 +416,7 @@ def main(argv=None):
     ap.add_argument("--tune-rep", type=int, default=3)
     ap.add_argument("--tile", type=str, default="", help="fixed tile bx,by,ry,dz,vw,xcd,pf (skips the search)")
     ap.add_argument("--compare-steps", type=int, default=200, help="steps timed for plain and default tiles")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-two-step", action="store_true", help="search one-step tiles only")
@@ -548,7 +548,7 @@ def main(argv=None):
         "metric": METRIC, "value": round(gpts, 3), "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{cfg['name']} layered model, order {2 * args.radius} (R={args.radius}) {6 * args.radius + 1}-point star, "
+        "config": {"workload": f"{cfg['name']} model, order {2 * args.radius} (R={args.radius}) {6 * args.radius + 1}-point star, "
                                f"FP32, Ricker source, {args.steps} timed steps",
                    "grid": [n, n, n], "radius": args.radius, "tile": tile, "tune": tune,
                    "plain_tiling": compare.get("plain_tiling"), "default_tile": compare.get("default_tile"),

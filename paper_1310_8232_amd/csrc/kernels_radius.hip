@@ -1,6 +1,7 @@
 // Instantiations of the sweep kernels for one radius (RADIUS is set on the
 // compiler command line; the library links one object per radius).
 #include "sweep.hpp"
+#include "sweep2.hpp"
 
 #ifndef RADIUS
 #error "compile with -DRADIUS=<3|4|5>"
