@@ -434,8 +434,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        print(f"bench.py: the sweep runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding across GPUs is a design note only).", file=sys.stderr)
         return 2
 
     import numpy as np

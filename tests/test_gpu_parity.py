@@ -5,6 +5,7 @@ arithmetic); bit-identical outputs across every tile shape, march depth, XCD
 order and the plain-tiling kernel (all use one canonical FP32 operation
 order); kappa bit-identical to the FP64 formula rounded once.
 """
+import os
 import sys
 import time
 
@@ -269,3 +270,49 @@ def test_full_size_512_tuned_default_plain():
             assert_close(unm1, ref_nm1, what="u^2")
         else:
             assert np.array_equal(un, base[0]) and np.array_equal(unm1, base[1])
+
+
+def _throughput_workload_vs_oracle(nt):
+    # The throughput workload exactly as the bench runs it (512^3 layered
+    # model, source at the centre, from rest), with a searched tile, against
+    # the FP64 oracle after nt steps.
+    c = workloads.config_layered(512, 512, 512, nt=nt)
+    log(f"case: 512^3 throughput workload from rest, searched tile, {nt} steps vs oracle")
+    prop = p.Propagator(cuda(c["v"]), c["h"], c["dt"], 4, vmax=c["vmax"])
+    rep, _, _ = prop.tune(parts=3, n_iter=5, n_rep=2)
+    tile = prop.tile
+    del prop
+    torch.cuda.empty_cache()
+    un, unm1, _ = gpu_run(c["v"], c["h"], c["dt"], c["vmax"], 4, nt, src_idx=c["src_idx"],
+                          amp=c["amp"].reshape(-1, 1), tile=tile)
+    log(f"  tile {tile.as_dict()}")
+    t0 = time.time()
+    kap = oracle.kappa(c["v"], c["dt"], c["h"])
+    amp = c["amp"].reshape(-1, 1).astype(np.float64)
+    ref_n = np.zeros(kap.shape)
+    ref_nm1 = np.zeros(kap.shape)
+    for it in range(0, nt, 50):  # in chunks, with a progress line per chunk
+        k = min(50, nt - it)
+        ref_n, ref_nm1 = oracle.leapfrog(kap, ref_n, ref_nm1, 4, k, it0=it, src_idx=c["src_idx"], amp=amp)
+        log(f"  oracle {it + k}/{nt} steps, {time.time() - t0:.0f}s")
+    return (oracle.rel_l2(un, ref_n), oracle.rel_l2(unm1, ref_nm1)), (un, unm1, ref_n, ref_nm1)
+
+
+@pytest.mark.slow
+def test_throughput_workload_512_100_steps():
+    (e1, e2), (un, unm1, _, _) = _throughput_workload_vs_oracle(100)
+    log(f"  u^100 rel_l2 {e1:.3e}   u^99 rel_l2 {e2:.3e}")
+    assert np.all(np.isfinite(un)) and np.all(np.isfinite(unm1))
+    assert e1 <= TOL and e2 <= TOL
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("P1310_LONG"),
+                    reason="the 1000-step FP64 oracle run at 512^3 takes several minutes of host time; "
+                           "set P1310_LONG=1 to run it")
+def test_throughput_workload_512_1000_steps():
+    # FP32 rounding grows about linearly with the step count (1e-5 holds at
+    # 100 steps); 2e-4 is the sanity bound at 1000.
+    (e1, e2), _ = _throughput_workload_vs_oracle(1000)
+    log(f"  u^1000 rel_l2 {e1:.3e}   u^999 rel_l2 {e2:.3e}")
+    assert e1 <= 2e-4 and e2 <= 2e-4
