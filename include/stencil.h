@@ -77,7 +77,8 @@ typedef struct {
     int32_t by;     /* threads along y */
     int32_t ry;     /* rows per thread along y (ZMARCH) */
     int32_t dz;     /* planes per workgroup along z (ZMARCH); threads along z (PLAIN) */
-    int32_t vw;     /* x points per thread: 4 (needs nx % 4 == 0) or 1; 0 = pick */
+    int32_t vw;     /* x points per thread: 4, 2 (ZMARCH, FP32 storage) or 1; must divide nx;
+                       0 = the widest that divides nx */
     int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
     int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2) */
 } stencil_tile;
@@ -155,7 +156,8 @@ void stencil_destroy(stencil_ctx *ctx);
 stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void *stream);
 
 /* (Wavefield arguments of the stepping calls are in the context's storage
- * type; with vw = 4 they must be aligned to 4 values, kappa to 16 bytes.) */
+ * type; with a tile of vw > 1 they must be aligned to vw values and kappa
+ * to 4*vw bytes, else EINVAL.) */
 
 /* stencil_step with the output in its own buffer: reads u_cur = u^{it} and
  * u_prev = u^{it-1}, writes u^{it+1} (sources included) to u_next. u_next may
@@ -179,7 +181,8 @@ stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_
  * overwrites u_prev_next with u^{it+1}, then injects the sources (src may
  * be NULL). Requires it < src->nt when src is given (EINVAL). u_cur and
  * u_prev_next must not overlap (EALIAS); kappa must not overlap
- * u_prev_next. Pointers must be 16-byte aligned when the tile uses vw = 4. */
+ * u_prev_next. Pointers must be aligned to vw values (kappa: 4*vw bytes)
+ * when the tile uses vw > 1. */
 stencil_status stencil_step(stencil_ctx *ctx, const void *kappa, const void *u_cur,
                             void *u_prev_next, int64_t it, const stencil_src *src, void *stream);
 
@@ -286,8 +289,9 @@ stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out);
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
 /* Compiled ZMARCH tiles for a radius and storage type, with vw = 4
- * (vec4 != 0) or 1, dz = 0. Writes at most cap entries to out (out may be
- * NULL) and returns the total count, or a negative stencil_status. */
+ * (vec4 = 1), 2 (vec4 = 2) or 1 (vec4 = 0), dz = 0. Writes at most cap
+ * entries to out (out may be NULL) and returns the total count, or a negative
+ * stencil_status. */
 int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stencil_tile *out, int32_t cap);
 
 /* Compiled two-step tiles (kind ZMARCH2, dz = 0) for a radius, FP32 storage. */

@@ -12,6 +12,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <initializer_list>
 #include <vector>
 
 #include "internal.h"
@@ -147,6 +148,34 @@ int64_t npoints(const stencil_ctx *c) { return c->d.nx * c->d.ny * c->d.nz; }
 
 bool vec4_ok(const stencil_ctx *c) { return c->d.nx % 4 == 0; }
 
+bool has_vw(const stencil_ctx *ctx, int vw)
+{
+    for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
+        const ZVariant *v = p1310::zmarch_variant(i);
+        if (v->R == ctx->R && v->st == ctx->st && v->vw == vw) return true;
+    }
+    return false;
+}
+
+// Widest x vector that divides nx and has compiled one-step kernels.
+int auto_vw(const stencil_ctx *ctx)
+{
+    if (ctx->d.nx % 4 == 0) return 4;
+    if (ctx->d.nx % 2 == 0 && has_vw(ctx, 2)) return 2;
+    return 1;
+}
+
+// Vector accesses of vw values need kappa on 4*vw-byte boundaries and the
+// wavefields on vw-value boundaries.
+bool vec_aligned(const stencil_ctx *ctx, int vw, const void *kappa, std::initializer_list<const void *> fields)
+{
+    if (vw <= 1) return true;
+    if ((uintptr_t)kappa & (uintptr_t)(4 * vw - 1)) return false;
+    for (const void *f : fields)
+        if ((uintptr_t)f & (uintptr_t)(vw * ctx->es - 1)) return false;
+    return true;
+}
+
 const ZVariant *find_variant(const stencil_ctx *ctx, const stencil_tile &t)
 {
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
@@ -190,7 +219,7 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     }
     if (t.kind == STENCIL_TILE_ZMARCH2) {
         if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
-        if (t.vw == 4 && !vec4_ok(ctx)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
+        if (t.vw < 1 || d.nx % t.vw) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx");
         t.ry = 1;
         const Z2Variant *v = find_variant2(ctx, t);
         if (!v) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled two-step kernel for this (bx, by, vw), radius, storage");
@@ -205,9 +234,8 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
         return STENCIL_OK;
     }
     if (t.kind != STENCIL_TILE_ZMARCH) return fail(ctx, STENCIL_EUNSUPPORTED, "unknown tile kind");
-    if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
-    if (t.vw == 4 && !vec4_ok(ctx))
-        return fail(ctx, STENCIL_EUNSUPPORTED, "vw = 4 needs nx % 4 == 0");
+    if (t.vw == 0) t.vw = auto_vw(ctx);
+    if (t.vw < 1 || d.nx % t.vw) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx");
     if (!find_variant(ctx, t))
         return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
     if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
@@ -240,11 +268,17 @@ stencil_tile default_tile(const stencil_ctx *ctx)
         return t;
     }
     t.kind = STENCIL_TILE_ZMARCH;
-    if (vec4_ok(ctx)) {
+    const int vw = auto_vw(ctx);
+    if (vw == 4) {
         t.bx = 16;
         t.by = 8;
         t.ry = 2;
         t.vw = 4;
+    } else if (vw == 2) {
+        t.bx = 64;
+        t.by = 4;
+        t.ry = 1;
+        t.vw = 2;
     } else {
         t.bx = 64;
         t.by = 4;
@@ -430,8 +464,8 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
 {
     std::vector<stencil_tile> out;
     const stencil_desc &d = ctx->d;
-    const int vw = vec4_ok(ctx) ? 4 : 1;
     if (o.temporal == 2) {
+        const int vw = vec4_ok(ctx) ? 4 : 1;
         // Two-step shapes x march depths x XCD order.
         const int64_t dzs[] = {16, 32, 64, 128, 256, d.nz};
         for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
@@ -447,10 +481,13 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
         }
         return out;
     }
+    // The widest vector width that divides nx; two-point vectors are timed
+    // against one-point ones (their rows need not be 16-byte aligned).
+    const int vw = auto_vw(ctx);
     std::vector<const ZVariant *> vars;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R == ctx->R && v->st == ctx->st && v->vw == vw) vars.push_back(v);
+        if (v->R == ctx->R && v->st == ctx->st && (v->vw == vw || (vw == 2 && v->vw == 1))) vars.push_back(v);
     }
     if (zmarch_possible(ctx) && !vars.empty()) {
         if (o.parts < 2) {
@@ -759,10 +796,8 @@ stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_
         for (int j = i + 1; j < 4; ++j)
             if (overlaps(f[i], f[j], ub)) return fail(ctx, STENCIL_EALIAS, "the four wavefields must not overlap");
     }
-    if (ctx->tile2.vw == 4 &&
-        (((uintptr_t)kappa & 15u) || (((uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next |
-                                       (uintptr_t)u_next2) & (uintptr_t)(4 * ctx->es - 1))))
-        return fail(ctx, STENCIL_EINVAL, "kappa must be 16-byte and the wavefields 4-value aligned for vw = 4");
+    if (!vec_aligned(ctx, ctx->tile2.vw, kappa, {u_cur, u_prev, u_next, u_next2}))
+        return fail(ctx, STENCIL_EINVAL, "kappa must be 4*vw-byte and the wavefields vw-value aligned");
     if (src && src->n != 0) {
         if (src->n > 1) return fail(ctx, STENCIL_EUNSUPPORTED, "two-step launches take at most one source");
         if (!src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
@@ -782,7 +817,7 @@ int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stenci
     int32_t n = 0;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R != radius || v->st != storage || v->vw != (vec4 ? 4 : 1)) continue;
+        if (v->R != radius || v->st != storage || v->vw != (vec4 == 2 ? 2 : (vec4 ? 4 : 1))) continue;
         if (out && n < cap) {
             stencil_tile t = {};
             t.kind = STENCIL_TILE_ZMARCH;
@@ -820,9 +855,8 @@ stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *
     if (overlaps2(kappa, kbytes, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps the output");
     if (u_prev != u_next && overlaps(u_prev, u_next, bytes))
         return fail(ctx, STENCIL_EALIAS, "u_prev partially overlaps the output");
-    if (ctx->tile.vw == 4 && (((uintptr_t)kappa & 15u) ||
-                              (((uintptr_t)u_cur | (uintptr_t)u_prev | (uintptr_t)u_next) & (uintptr_t)(4 * ctx->es - 1))))
-        return fail(ctx, STENCIL_EINVAL, "kappa must be 16-byte and the wavefields 4-value aligned for vw = 4");
+    if (ctx->tile.kind == STENCIL_TILE_ZMARCH && !vec_aligned(ctx, ctx->tile.vw, kappa, {u_cur, u_prev, u_next}))
+        return fail(ctx, STENCIL_EINVAL, "kappa must be 4*vw-byte and the wavefields vw-value aligned");
     if (src && src->n != 0) {
         if (src->n < 0 || !src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
         if (it < 0 || it >= src->nt) return fail(ctx, STENCIL_EINVAL, "step index outside the source's samples");
@@ -1135,8 +1169,8 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             delete bt;
             return STENCIL_EALIAS;
         }
-        if (sh.ctx->tile.vw == 4 &&
-            (((uintptr_t)sh.kappa & 15u) || (((uintptr_t)sh.u_a | (uintptr_t)sh.u_b) & (uintptr_t)(4 * sh.ctx->es - 1)))) {
+        const stencil_tile &tt = tiles ? tiles[i] : sh.ctx->tile;
+        if (tt.kind == STENCIL_TILE_ZMARCH && !vec_aligned(sh.ctx, tt.vw, sh.kappa, {sh.u_a, sh.u_b})) {
             delete bt;
             return STENCIL_EINVAL;
         }

@@ -49,6 +49,9 @@ static const ZVariant kTable[] = {
     ZV(16, 4, 2, 4, 1) ZV(16, 8, 1, 4, 1) ZV(16, 8, 2, 4, 1) ZV(16, 16, 1, 4, 1)
     ZV(32, 4, 2, 4, 1) ZV(32, 8, 1, 4, 1) ZV(64, 4, 1, 4, 1)
     ZV(64, 4, 1, 1, 0) ZV(64, 4, 2, 1, 0) ZV(32, 8, 2, 1, 0) ZV(64, 8, 1, 1, 0)
+    ZV(128, 4, 1, 1, 0) ZV(128, 2, 2, 1, 0) ZV(256, 2, 1, 1, 0)
+    ZV(64, 4, 1, 2, 0) ZV(64, 4, 2, 2, 0) ZV(64, 8, 1, 2, 0) ZV(32, 8, 1, 2, 0) ZV(32, 8, 2, 2, 0)
+    ZV(128, 2, 1, 2, 0) ZV(128, 4, 1, 2, 0) ZV(64, 4, 1, 2, 1) ZV(128, 2, 1, 2, 1)
     ZV16(kF16) ZV16(kBF16)
 };
 

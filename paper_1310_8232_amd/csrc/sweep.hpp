@@ -19,6 +19,7 @@ namespace p1310 {
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 
 // A voffset beyond every buffer window (windows are < 2 GiB): buffer loads
 // there return 0 and buffer stores there are dropped. This gives the zero
@@ -44,6 +45,8 @@ __device__ __forceinline__ Vec<VW> bload(rsrc_t r, uint32_t voff, uint32_t soff)
 {
     if constexpr (VW == 4) {
         return __builtin_bit_cast(Vec<4>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+    } else if constexpr (VW == 2) {
+        return __builtin_bit_cast(Vec<2>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
     } else {
         return __builtin_bit_cast(Vec<1>, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
     }
@@ -54,6 +57,8 @@ __device__ __forceinline__ void bstore(const Vec<VW> &v, rsrc_t r, uint32_t voff
 {
     if constexpr (VW == 4) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, voff, soff, AUX);
+    } else if constexpr (VW == 2) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, voff, soff, AUX);
     } else {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, voff, soff, AUX);
     }
@@ -75,8 +80,6 @@ struct StorageBytes {
     static constexpr int value = sizeof(ST);
 };
 
-typedef unsigned int u2v __attribute__((ext_vector_type(2)));
-
 template <typename ST, int VW, int AUX>
 __device__ __forceinline__ Vec<VW> uload(rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -87,6 +90,11 @@ __device__ __forceinline__ Vec<VW> uload(rsrc_t r, uint32_t voff, uint32_t soff)
         typedef float f4 __attribute__((ext_vector_type(4)));
         const s4 h = __builtin_bit_cast(s4, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
         return __builtin_bit_cast(Vec<4>, __builtin_convertvector(h, f4));
+    } else if constexpr (VW == 2) {
+        typedef ST s2 __attribute__((ext_vector_type(2)));
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const s2 h = __builtin_bit_cast(s2, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
+        return __builtin_bit_cast(Vec<2>, __builtin_convertvector(h, f2));
     } else {
         Vec<1> v;
         v.a[0] = (float)__builtin_bit_cast(ST, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX));
@@ -104,6 +112,11 @@ __device__ __forceinline__ void ustore(const Vec<VW> &v, rsrc_t r, uint32_t voff
         typedef float f4 __attribute__((ext_vector_type(4)));
         const s4 h = __builtin_convertvector(__builtin_bit_cast(f4, v), s4);
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, h), r, voff, soff, AUX);
+    } else if constexpr (VW == 2) {
+        typedef ST s2 __attribute__((ext_vector_type(2)));
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const s2 h = __builtin_convertvector(__builtin_bit_cast(f2, v), s2);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, h), r, voff, soff, AUX);
     } else {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (ST)v.a[0]), r, voff, soff, AUX);
     }
@@ -157,7 +170,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     constexpr int NXH = 2 * TY * HV;       // x-halo vectors per plane
     constexpr int NH = NXH + 2 * R * BX;   // + y-halo vectors
     constexpr int NHI = (NH + NT - 1) / NT;
-    static_assert(LBUF % 4 == 0 || VW == 1, "LDS buffers must stay 16-byte aligned");
+    static_assert(LBUF % VW == 0, "LDS buffers must stay vector aligned");
     using V = Vec<VW>;
 
     __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];

@@ -46,8 +46,8 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     constexpr int NXH = 2 * EY * HV;
     constexpr int NH = NXH + 2 * R * BX;
     constexpr int NHI = (NH + NT - 1) / NT;
-    static_assert(LBUF % 4 == 0 || VW == 1, "LDS buffers must stay 16-byte aligned");
-    static_assert(L2BUF % 4 == 0 || VW == 1, "LDS buffers must stay 16-byte aligned");
+    static_assert(LBUF % VW == 0, "LDS buffers must stay vector aligned");
+    static_assert(L2BUF % VW == 0, "LDS buffers must stay vector aligned");
     using V = Vec<VW>;
 
     __shared__ __attribute__((aligned(16))) float lds1[2 * LBUF];

@@ -215,3 +215,41 @@ def test_two_step_tile_and_validation():
         p.stencil_get_tile2(ctx)
     assert e.value.status == p.EUNSUPPORTED
     p.stencil_destroy(ctx)
+
+
+def test_vector_width_follows_nx():
+    # nx % 4 == 2: two-point tiles by default, four-point tiles rejected;
+    # odd nx: one-point tiles only. Alignment is checked per vector width.
+    ctx = _init(nx=70, ny=20, nz=12)
+    assert p.stencil_get_tile(ctx).vw == 2
+    two = p.stencil_list_tiles(4, 2)
+    assert len(two) >= 5 and all(t.vw == 2 for t in two)
+    for t in two:
+        t.dz = 8
+        p.stencil_set_tile(ctx, t)
+        assert p.stencil_get_tile(ctx).vw == 2
+    four = p.stencil_list_tiles(4, True)[0]
+    four.dz = 8
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, four)
+    assert e.value.status == p.EUNSUPPORTED and "divide" in p.stencil_last_error(ctx)
+    n = 70 * 20 * 12 * 4
+    base = 1 << 40
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base, base + 2 * n + 4, base + 4 * n, 0, None, 0)
+    assert e.value.status == p.EINVAL  # one value off for vw = 2
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base + 4, base + 2 * n, base + 4 * n, 0, None, 0)
+    assert e.value.status == p.EINVAL  # kappa not 8-byte aligned
+    p.stencil_destroy(ctx)
+    ctx = _init(nx=71, ny=20, nz=12)
+    assert p.stencil_get_tile(ctx).vw == 1
+    two[0].dz = 8
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, two[0])
+    assert e.value.status == p.EUNSUPPORTED
+    p.stencil_destroy(ctx)
+    # 16-bit storage has no two-point kernels: nx % 4 == 2 falls back to one.
+    ctx = _init(nx=70, ny=20, nz=12, storage="f16", storage_scale=1024.0)
+    assert p.stencil_get_tile(ctx).vw == 1
+    p.stencil_destroy(ctx)

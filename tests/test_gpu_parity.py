@@ -110,9 +110,11 @@ def _random_case(nx, ny, nz, seed, R=4):
     return v, dt, vmax, u0, um1
 
 
-def _tiles(R, vec4, dzs):
+def _tiles(R, nx, dzs):
+    # Every compiled vector width that divides nx (4, 2, 1 points per thread).
     out = []
-    for t in p.stencil_list_tiles(R, vec4):
+    ts = [t for w in (4, 2, 1) if nx % w == 0 for t in p.stencil_list_tiles(R, {4: 1, 2: 2, 1: 0}[w])]
+    for t in ts:
         for dz in dzs:
             for xcd in (1, 0):
                 out.append(p.make_tile(p.TILE_ZMARCH, t.bx, t.by, t.ry, dz, t.vw, xcd, t.pf))
@@ -122,7 +124,8 @@ def _tiles(R, vec4, dzs):
 
 
 @pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (3, (72, 45, 37)), (5, (72, 45, 37)),
-                                     (4, (61, 45, 37)), (5, (61, 29, 23)), (4, (260, 67, 19))])
+                                     (4, (61, 45, 37)), (5, (61, 29, 23)), (4, (260, 67, 19)),
+                                     (4, (70, 45, 37)), (5, (250, 29, 23)), (3, (66, 20, 12))])
 def test_tile_invariance_and_oracle(R, shape):
     nx, ny, nz = shape
     v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=100 + R, R=R)
@@ -130,7 +133,7 @@ def test_tile_invariance_and_oracle(R, shape):
     log(f"case: random fields {nx}x{ny}x{nz} R={R}, {nsteps} steps, every tile")
     ref_n, ref_nm1 = oracle_run(v, 10.0, dt, R, nsteps, u0, um1)
     base = None
-    tiles = _tiles(R, nx % 4 == 0, (1, 7, 16, nz))
+    tiles = _tiles(R, nx, (1, 7, 16, nz))
     for t in tiles:
         un, unm1, _ = gpu_run(v, 10.0, dt, vmax, R, nsteps, u0, um1, tile=t)
         if base is None:
