@@ -15,7 +15,9 @@ dJ/dm = -(h^2/dt^2) sum_n mu^{n+1} (u^{n+1} - 2u^n + u^{n-1}), m = 1/v^2.
 Checkpoints: (u^n, u^{n-1}) every C steps during the forward pass; the
 backward pass recomputes each segment of C steps from its checkpoint into a
 buffer of C+2 wavefields (no copies: the out-of-place step writes each level
-into its slot), then runs the segment's adjoint steps in reverse.
+into its slot), then runs the segment's adjoint steps in reverse. With C = 0
+every level is kept (nt + 2 wavefields; 31 GiB at 256^3 and 500 steps) and
+nothing is recomputed.
 """
 from __future__ import annotations
 
@@ -47,12 +49,25 @@ def _copy(dst: torch.Tensor, src: torch.Tensor):
     stencil_stream_probe(src, None, None, dst, src.numel() * 4)
 
 
-def forward(prop: Propagator, survey: Survey, checkpoint_every: int = 0):
+def forward(prop: Propagator, survey: Survey, checkpoint_every: int = 0, keep_levels: bool = False):
     """Forward pass from rest. Returns (traces [nt, nrec] float32,
     checkpoints {n: (u^n, u^{n-1})} every `checkpoint_every` steps (none if 0),
-    final (u^nt, u^{nt-1}))."""
+    final (u^nt, u^{nt-1})).
+
+    keep_levels=True instead keeps every time level: one [nt+2, nz, ny, nx]
+    buffer with u^n in row n+1, each step written out of place into its own
+    row (no copies); the checkpoint dict is then {"levels": buffer}."""
     nt = survey.nt
     src = survey.src()
+    if keep_levels:
+        levels = torch.empty((nt + 2,) + tuple(prop.shape), device=prop.device)
+        levels[0].zero_()
+        levels[1].zero_()
+        traces = torch.empty((nt, survey.rec_idx.numel()), device=prop.device)
+        for n in range(nt):
+            stencil_step_to(prop.ctx, prop.kappa, levels[n + 1], levels[n], levels[n + 2], n, src)
+            stencil_sample(prop.ctx, levels[n + 2], survey.rec_idx, traces[n])
+        return traces, {"levels": levels}, (levels[nt + 1], levels[nt])
     a = torch.zeros(prop.shape, device=prop.device)
     b = torch.zeros(prop.shape, device=prop.device)
     traces = torch.empty((nt, survey.rec_idx.numel()), device=prop.device)
@@ -86,6 +101,12 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
     grad = torch.zeros(prop.shape, dtype=torch.float64, device=prop.device)
     mu_cur = torch.zeros(prop.shape, device=prop.device)   # mu^{k+1}
     mu_prev = torch.zeros(prop.shape, device=prop.device)  # mu^{k+2}
+    if "levels" in ckpts:  # every level kept: no recompute
+        L = ckpts["levels"]  # L[n + 1] = u^n
+        for k in range(nt, 0, -1):
+            stencil_adjoint_step(prop.ctx, prop.kappa, mu_cur, mu_prev, k - 1, rsrc, L[k + 1], L[k], L[k - 1], grad)
+            mu_cur, mu_prev = mu_prev, mu_cur
+        return grad
     buf = torch.empty((C,) + tuple(prop.shape), device=prop.device)
     for n0 in sorted(ckpts, reverse=True):
         n1 = min(n0 + C, nt)
@@ -103,10 +124,15 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
 
 
 def misfit_gradient(prop: Propagator, survey: Survey, observed: torch.Tensor, checkpoint_every: int = 50):
-    """(J float64 device scalar, dJ/dm float64 field, traces)."""
-    if checkpoint_every < 1:
-        raise ValueError("checkpoint_every must be >= 1")
-    traces, ckpts, _ = forward(prop, survey, checkpoint_every)
+    """(J float64 device scalar, dJ/dm float64 field, traces).
+
+    checkpoint_every = C > 0 keeps (u^n, u^{n-1}) every C steps and recomputes
+    each segment in the backward pass (memory: 2 nt/C + C wavefields);
+    checkpoint_every = 0 keeps every level instead (nt + 2 wavefields, no
+    recompute), which HBM holds for moderate grids and step counts."""
+    if checkpoint_every < 0:
+        raise ValueError("checkpoint_every must be >= 0")
+    traces, ckpts, _ = forward(prop, survey, checkpoint_every, keep_levels=checkpoint_every == 0)
     J, resid = misfit(traces, observed)
     grad = backward(prop, survey, resid, ckpts, checkpoint_every)
     return J, grad, traces
@@ -123,7 +149,9 @@ class SlownessMisfit(torch.autograd.Function):
     def forward(ctx, m, survey: Survey, observed, h: float, dt: float, radius: int = 4,
                 checkpoint_every: int = 50, tile=None):
         prop = Propagator(m.detach().contiguous(), h, dt, radius, slowness2=True, tile=tile)
-        traces, ckpts, _ = forward(prop, survey, checkpoint_every)
+        if checkpoint_every < 0:
+            raise ValueError("checkpoint_every must be >= 0")
+        traces, ckpts, _ = forward(prop, survey, checkpoint_every, keep_levels=checkpoint_every == 0)
         J, resid = misfit(traces, observed)
         ctx.state = (prop, survey, resid, ckpts, checkpoint_every)
         return J
