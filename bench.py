@@ -96,10 +96,18 @@ def cpu_baseline(cfg, budget_s: float):
     t2 = time.perf_counter() - t0
     steps = 1 + more
     npts = kap.size
-    return {"value": npts * steps / (t1 + t2) / 1e9, "unit": "Gpt/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # The same oracle on one thread, one step (the next step of the run).
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.leapfrog(kap, uc, up, cfg["radius"], 1, it0=1, src_idx=cfg["src_idx"], amp=amp)
+    t3 = time.perf_counter() - t0
+    oracle.set_num_threads(cores)
+    return {"value": npts * steps / (t1 + t2) / 1e9, "unit": "Gpt/s", "cores": cores,
             "kind": "oracle",
             "sample": f"FP64 oracle, {steps} leapfrog steps of the same {cfg['nx']}x{cfg['ny']}x{cfg['nz']} "
-                      f"layered workload from rest (source on), {t1 + t2:.1f} s"}
+                      f"layered workload from rest (source on), {t1 + t2:.1f} s",
+            "single_thread": {"value": npts / t3 / 1e9, "unit": "Gpt/s", "sample": f"1 step, {t3:.1f} s"}}
 
 
 def stream_rate(mib: int, n_in: int, steps: int, warmup: int):

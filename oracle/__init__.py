@@ -56,6 +56,8 @@ def _load():
     lib.oracle_leapfrog.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -137,6 +139,11 @@ def leapfrog(kap: np.ndarray, u_cur: np.ndarray, u_prev: np.ndarray, R: int,
 def num_threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later loops (for timing on one core)."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
