@@ -440,6 +440,8 @@ def main(argv=None):
     ap.add_argument("--tune-iter", type=int, default=10)
     ap.add_argument("--tune-rep", type=int, default=3)
     ap.add_argument("--tile", type=str, default="", help="fixed tile bx,by,ry,dz,vw,xcd,pf (skips the search)")
+    ap.add_argument("--tile2", type=str, default="",
+                    help="fixed two-step tile bx,by,dz,vw,xcd,pf: runs two-step launches (skips the search)")
     ap.add_argument("--compare-steps", type=int, default=200, help="steps timed for plain and default tiles")
     ap.add_argument("--cpu-budget", type=float, default=16.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -496,7 +498,11 @@ def main(argv=None):
 
     tune = None
     temporal = 1
-    if args.tile:
+    if args.tile2:
+        bx, by, dz, vw, xcd, pf = [int(x) for x in args.tile2.split(",")]
+        prop.tile = p.make_tile(p.TILE_ZMARCH2, bx, by, 1, dz, vw, xcd, pf)
+        temporal = 2
+    elif args.tile:
         f = [int(x) for x in args.tile.split(",")]
         prop.tile = p.make_tile(p.TILE_ZMARCH, *f)
     else:

@@ -38,7 +38,15 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     constexpr int HV = HX / VW;
     constexpr int OX = EX - 2 * HX, OY = EY - 2 * R;
     static_assert(OX > 0 && OY > 0, "extended tile too small for the radius");
-    constexpr int LW = EX + 2 * HX;
+    // LDS row of the u^n plane: EX + 2HX floats, padded when a row of BX
+    // threads is not a whole number of 16-lane groups (BX = 18, 8): then a
+    // 16-lane b128 access spans two rows, and (LW/4 - BX) % 16 == 0 makes the
+    // second row continue the first one's 16-byte bank-group sequence, so
+    // the access is conflict-free.
+    constexpr int LW0 = EX + 2 * HX;
+    constexpr bool kStraddle = VW == 4 && (BX % 16) != 0;
+    constexpr int LW = kStraddle ? LW0 + ((((BX - LW0 / 4) % 16) + 16) % 16) * 4 : LW0;
+    static_assert(!kStraddle || ((LW / 4 - BX) % 16 == 0 && LW % 4 == 0), "LDS row padding");
     constexpr int LROWS = EY + 2 * R;
     constexpr int LBUF = LROWS * LW + VW;
     constexpr int L2BUF = EY * EX;
