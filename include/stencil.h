@@ -77,8 +77,8 @@ typedef struct {
     int32_t by;     /* threads along y */
     int32_t ry;     /* rows per thread along y (ZMARCH) */
     int32_t dz;     /* planes per workgroup along z (ZMARCH); threads along z (PLAIN) */
-    int32_t vw;     /* x points per thread: 4, 2 (ZMARCH, FP32 storage) or 1; must divide nx;
-                       0 = the widest that divides nx */
+    int32_t vw;     /* x points per thread: 8 (ZMARCH, 16-bit storage), 4, 2 (ZMARCH, FP32
+                       storage) or 1; must divide nx; 0 = the widest that divides nx */
     int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
     int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2) */
 } stencil_tile;
@@ -289,9 +289,9 @@ stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out);
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
 /* Compiled ZMARCH tiles for a radius and storage type, with vw = 4
- * (vec4 = 1), 2 (vec4 = 2) or 1 (vec4 = 0), dz = 0. Writes at most cap
- * entries to out (out may be NULL) and returns the total count, or a negative
- * stencil_status. */
+ * (vec4 = 1), 8 (vec4 = 8), 2 (vec4 = 2) or 1 (vec4 = 0), dz = 0. Writes at
+ * most cap entries to out (out may be NULL) and returns the total count, or a
+ * negative stencil_status. */
 int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stencil_tile *out, int32_t cap);
 
 /* Compiled two-step tiles (kind ZMARCH2, dz = 0) for a radius, FP32 storage. */

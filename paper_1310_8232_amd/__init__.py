@@ -340,7 +340,7 @@ def stencil_set_tile(ctx, tile: StencilTile):
 
 def stencil_list_tiles(radius: int, vec4: bool = True, storage=F32):
     """Compiled one-step tiles; vec4: True/1 = four x points per thread,
-    2 = two, False/0 = one."""
+    8 = eight (16-bit storage), 2 = two, False/0 = one."""
     st = STORAGES[storage] if isinstance(storage, str) else int(storage)
     n = _lib.stencil_list_tiles(radius, int(vec4), st, None, 0)
     _check(min(n, 0))

@@ -160,6 +160,7 @@ bool has_vw(const stencil_ctx *ctx, int vw)
 // Widest x vector that divides nx and has compiled one-step kernels.
 int auto_vw(const stencil_ctx *ctx)
 {
+    if (ctx->d.nx % 8 == 0 && has_vw(ctx, 8)) return 8;
     if (ctx->d.nx % 4 == 0) return 4;
     if (ctx->d.nx % 2 == 0 && has_vw(ctx, 2)) return 2;
     return 1;
@@ -269,7 +270,7 @@ stencil_tile default_tile(const stencil_ctx *ctx)
     }
     t.kind = STENCIL_TILE_ZMARCH;
     const int vw = auto_vw(ctx);
-    if (vw == 4) {
+    if (vw >= 4) {
         t.bx = 16;
         t.by = 8;
         t.ry = 2;
@@ -481,13 +482,15 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
         }
         return out;
     }
-    // The widest vector width that divides nx; two-point vectors are timed
-    // against one-point ones (their rows need not be 16-byte aligned).
+    // The widest vector width that divides nx, timed against the next
+    // narrower one: two-point against one-point vectors (their rows need not
+    // be 16-byte aligned), eight-point (16-bit storage) against four-point.
     const int vw = auto_vw(ctx);
+    const int vw_alt = vw == 2 ? 1 : (vw == 8 ? 4 : vw);
     std::vector<const ZVariant *> vars;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R == ctx->R && v->st == ctx->st && (v->vw == vw || (vw == 2 && v->vw == 1))) vars.push_back(v);
+        if (v->R == ctx->R && v->st == ctx->st && (v->vw == vw || v->vw == vw_alt)) vars.push_back(v);
     }
     if (zmarch_possible(ctx) && !vars.empty()) {
         if (o.parts < 2) {
@@ -817,7 +820,7 @@ int32_t stencil_list_tiles(int32_t radius, int32_t vec4, int32_t storage, stenci
     int32_t n = 0;
     for (int i = 0; i < p1310::zmarch_variant_count(); ++i) {
         const ZVariant *v = p1310::zmarch_variant(i);
-        if (v->R != radius || v->st != storage || v->vw != (vec4 == 2 ? 2 : (vec4 ? 4 : 1))) continue;
+        if (v->R != radius || v->st != storage || v->vw != (vec4 == 2 || vec4 == 8 ? vec4 : (vec4 ? 4 : 1))) continue;
         if (out && n < cap) {
             stencil_tile t = {};
             t.kind = STENCIL_TILE_ZMARCH;

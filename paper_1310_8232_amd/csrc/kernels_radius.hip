@@ -27,12 +27,16 @@ namespace p1310 {
      zmarch_batch_kernel<RADIUS, BX, BY, RY, VW, PF, ST_##STT>, BX * BY, ZV_LDS(BX, BY, RY, VW)},
 #define ZV(BX, BY, RY, VW, PF) ZVS(BX, BY, RY, VW, PF, kF32)
 
-// 16-bit wavefield storage: a smaller set of shapes, radii 4 and 5.
+// 16-bit wavefield storage (radii 4 and 5): four- and eight-point vectors (an
+// eight-point vector of 16-bit values is one 16-byte access), one-point rows.
 #if RADIUS >= 4
 #define ZV16(STT)                                                                                \
     ZVS(16, 8, 1, 4, 0, STT) ZVS(16, 8, 2, 4, 0, STT) ZVS(32, 8, 1, 4, 0, STT)                  \
     ZVS(32, 4, 2, 4, 0, STT) ZVS(64, 4, 1, 4, 0, STT) ZVS(64, 4, 2, 4, 0, STT)                  \
-    ZVS(16, 16, 1, 4, 0, STT) ZVS(64, 4, 1, 4, 1, STT) ZVS(64, 4, 1, 1, 0, STT)
+    ZVS(16, 16, 1, 4, 0, STT) ZVS(64, 4, 1, 4, 1, STT) ZVS(64, 4, 1, 1, 0, STT)                  \
+    ZVS(128, 2, 1, 4, 0, STT) ZVS(32, 16, 1, 4, 0, STT) ZVS(64, 8, 1, 4, 0, STT)                 \
+    ZVS(16, 8, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 0, STT) ZVS(32, 4, 1, 8, 0, STT)                   \
+    ZVS(64, 4, 1, 8, 0, STT) ZVS(16, 16, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 1, STT)
 #else
 #define ZV16(STT)
 #endif

@@ -43,7 +43,17 @@ __device__ __forceinline__ rsrc_t make_rsrc(const float *base, uint32_t bytes)
 template <int VW, int AUX>
 __device__ __forceinline__ Vec<VW> bload(rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    if constexpr (VW == 4) {
+    if constexpr (VW == 8) {
+        Vec<8> v;
+        const Vec<4> lo = __builtin_bit_cast(Vec<4>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+        const Vec<4> hi = __builtin_bit_cast(Vec<4>, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16u, soff, AUX));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            v.a[e] = lo.a[e];
+            v.a[4 + e] = hi.a[e];
+        }
+        return v;
+    } else if constexpr (VW == 4) {
         return __builtin_bit_cast(Vec<4>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
     } else if constexpr (VW == 2) {
         return __builtin_bit_cast(Vec<2>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX));
@@ -55,7 +65,16 @@ __device__ __forceinline__ Vec<VW> bload(rsrc_t r, uint32_t voff, uint32_t soff)
 template <int VW, int AUX>
 __device__ __forceinline__ void bstore(const Vec<VW> &v, rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    if constexpr (VW == 4) {
+    if constexpr (VW == 8) {
+        Vec<4> lo, hi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            lo.a[e] = v.a[e];
+            hi.a[e] = v.a[4 + e];
+        }
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, lo), r, voff, soff, AUX);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, hi), r, voff + 16u, soff, AUX);
+    } else if constexpr (VW == 4) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, voff, soff, AUX);
     } else if constexpr (VW == 2) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, voff, soff, AUX);
@@ -85,6 +104,11 @@ __device__ __forceinline__ Vec<VW> uload(rsrc_t r, uint32_t voff, uint32_t soff)
 {
     if constexpr (sizeof(ST) == 4) {
         return bload<VW, AUX>(r, voff, soff);
+    } else if constexpr (VW == 8) {
+        typedef ST s8 __attribute__((ext_vector_type(8)));
+        typedef float f8 __attribute__((ext_vector_type(8)));
+        const s8 h = __builtin_bit_cast(s8, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
+        return __builtin_bit_cast(Vec<8>, __builtin_convertvector(h, f8));
     } else if constexpr (VW == 4) {
         typedef ST s4 __attribute__((ext_vector_type(4)));
         typedef float f4 __attribute__((ext_vector_type(4)));
@@ -107,6 +131,11 @@ __device__ __forceinline__ void ustore(const Vec<VW> &v, rsrc_t r, uint32_t voff
 {
     if constexpr (sizeof(ST) == 4) {
         bstore<VW, AUX>(v, r, voff, soff);
+    } else if constexpr (VW == 8) {
+        typedef ST s8 __attribute__((ext_vector_type(8)));
+        typedef float f8 __attribute__((ext_vector_type(8)));
+        const s8 h = __builtin_convertvector(__builtin_bit_cast(f8, v), s8);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, h), r, voff, soff, AUX);
     } else if constexpr (VW == 4) {
         typedef ST s4 __attribute__((ext_vector_type(4)));
         typedef float f4 __attribute__((ext_vector_type(4)));
@@ -173,7 +202,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     static_assert(LBUF % VW == 0, "LDS buffers must stay vector aligned");
     using V = Vec<VW>;
 
-    __shared__ __attribute__((aligned(16))) float lds[2 * LBUF];
+    __shared__ __attribute__((aligned(32))) float lds[2 * LBUF];
 
     // ---- tile of this workgroup (b = tile id within the grid) --------------
     const int tile_x = b % a.gx;

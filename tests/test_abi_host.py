@@ -253,3 +253,24 @@ def test_vector_width_follows_nx():
     ctx = _init(nx=70, ny=20, nz=12, storage="f16", storage_scale=1024.0)
     assert p.stencil_get_tile(ctx).vw == 1
     p.stencil_destroy(ctx)
+
+
+def test_eight_point_tiles_for_16bit_storage():
+    # 16-bit storage has eight-point tiles (one 16-byte access per lane) for
+    # nx % 8 == 0; FP32 storage has none.
+    assert p.stencil_list_tiles(4, 8, "f32") == []
+    for st in ("f16", "bf16"):
+        eight = p.stencil_list_tiles(4, 8, st)
+        assert len(eight) >= 4 and all(t.vw == 8 for t in eight)
+        ctx = _init(nx=64, ny=20, nz=12, storage=st, storage_scale=1024.0)
+        for t in eight:
+            t.dz = 8
+            p.stencil_set_tile(ctx, t)
+            assert p.stencil_get_tile(ctx).vw == 8
+        p.stencil_destroy(ctx)
+        ctx = _init(nx=68, ny=20, nz=12, storage=st, storage_scale=1024.0)
+        eight[0].dz = 8
+        with pytest.raises(p.StencilError) as e:
+            p.stencil_set_tile(ctx, eight[0])
+        assert e.value.status == p.EUNSUPPORTED
+        p.stencil_destroy(ctx)

@@ -77,14 +77,16 @@ def _random_state(prop, shape, seed):
 
 
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-@pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (5, (72, 45, 37)), (4, (61, 29, 23))])
+@pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (5, (72, 45, 37)), (4, (61, 29, 23)), (4, (76, 33, 21))])
 def test_16bit_tiles_bit_identical(storage, R, shape):
     nx, ny, nz = shape
     v = workloads.layered_model(nx, ny, nz, seed=11)
     dt, vmax = workloads.dt_for_courant(v, 10.0)
     log(f"case: {storage} R={R} {shape}, every 16-bit tile")
     tiles = []
-    for t in p.stencil_list_tiles(R, nx % 4 == 0, storage):
+    # Every vector width that divides nx: 8 (16-byte accesses), 4 and 1 points.
+    lists = [t for w, flag in ((8, 8), (4, 1), (1, 0)) if nx % w == 0 for t in p.stencil_list_tiles(R, flag, storage)]
+    for t in lists:
         for dz in (1, 7, nz):
             for xcd in (1, 0):
                 tiles.append(p.make_tile(p.TILE_ZMARCH, t.bx, t.by, t.ry, dz, t.vw, xcd, t.pf))
