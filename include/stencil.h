@@ -215,6 +215,18 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
                                     int64_t it, const stencil_src *resid, const void *u_next, const void *u_cur,
                                     const void *u_prev, double *grad, void *stream);
 
+/* The gradient terms of two consecutive adjoint steps k and k-1 (each run
+ * with grad = NULL) in one pass over memory:
+ *   grad += -(h^2/dt^2) * mu^k     * (u^k     - 2 u^{k-1} + u^{k-2})
+ *   grad += -(h^2/dt^2) * mu^{k-1} * (u^{k-1} - 2 u^{k-2} + u^{k-3})
+ * in this order, each term rounded as stencil_adjoint_step rounds it, so the
+ * result is the bits of the two accumulating adjoint steps. After the two
+ * steps mu^k is in their lam_cur buffer and mu^{k-1} in lam_prev_next. FP32
+ * fields, FP64 grad (must not overlap another field: EALIAS); FP32 storage
+ * only (EUNSUPPORTED). Capture-safe. */
+stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void *mu_km1, const void *u_k,
+                                 const void *u_km1, const void *u_km2, const void *u_km3, double *grad, void *stream);
+
 /* resid[i] = traces[i] - observed[i] (FP32, i < count; resid may be NULL) and
  * *misfit = 1/2 sum resid^2 accumulated in FP64 in a fixed order (device
  * double). All pointers are device memory. */

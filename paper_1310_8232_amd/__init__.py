@@ -100,6 +100,7 @@ _sig = {
     "stencil_sample": (_i32, [_vp, _vp, _vp, _i32, _vp, _vp]),
     "stencil_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp, _vp, _vp, _vp,
                                     _vp]),
+    "stencil_gradient2": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "stencil_batch_create": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
     "stencil_batch_step": (_i32, [_vp, _i64, _vp]),
@@ -246,6 +247,12 @@ def stencil_adjoint_step(ctx, kappa, lam_cur, lam_prev_next, it, resid: StencilS
     _check(_lib.stencil_adjoint_step(ctx, _ptr(kappa), _ptr(lam_cur), _ptr(lam_prev_next), int(it),
                                      ctypes.byref(resid) if resid is not None else None, _ptr(u_next), _ptr(u_cur),
                                      _ptr(u_prev), _ptr(grad), _stream(stream)), ctx)
+
+
+def stencil_gradient2(ctx, mu_k, mu_km1, u_k, u_km1, u_km2, u_km3, grad, stream=None):
+    """The gradient terms of adjoint steps k and k-1 in one pass (see the header)."""
+    _check(_lib.stencil_gradient2(ctx, _ptr(mu_k), _ptr(mu_km1), _ptr(u_k), _ptr(u_km1), _ptr(u_km2), _ptr(u_km3),
+                                  _ptr(grad), _stream(stream)), ctx)
 
 
 def stencil_misfit(traces, observed, resid, misfit, stream=None):

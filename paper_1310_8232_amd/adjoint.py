@@ -25,8 +25,8 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (Propagator, StencilSrc, make_src, stencil_adjoint_step, stencil_misfit, stencil_sample,
-               stencil_step, stencil_step_to, stencil_stream_probe)
+from . import (Propagator, StencilSrc, make_src, stencil_adjoint_step, stencil_gradient2, stencil_misfit,
+               stencil_sample, stencil_step, stencil_step_to, stencil_stream_probe)
 
 
 @dataclass
@@ -101,11 +101,30 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
     grad = torch.zeros(prop.shape, dtype=torch.float64, device=prop.device)
     mu_cur = torch.zeros(prop.shape, device=prop.device)   # mu^{k+1}
     mu_prev = torch.zeros(prop.shape, device=prop.device)  # mu^{k+2}
+    state = [mu_cur, mu_prev]
+
+    def adjoint_range(k_hi, k_lo, level):
+        # Adjoint steps k = k_hi .. k_lo + 1 with level(j) = u^j. Steps go in
+        # pairs whose two gradient terms share one pass over memory
+        # (stencil_gradient2: the bits of two accumulating steps); an odd
+        # last step accumulates on its own.
+        k = k_hi
+        while k > k_lo:
+            mc, mp = state
+            if k - 1 > k_lo:
+                stencil_adjoint_step(prop.ctx, prop.kappa, mc, mp, k - 1, rsrc)           # mu^k into mp
+                stencil_adjoint_step(prop.ctx, prop.kappa, mp, mc, k - 2, rsrc)           # mu^{k-1} into mc
+                stencil_gradient2(prop.ctx, mp, mc, level(k), level(k - 1), level(k - 2), level(k - 3), grad)
+                k -= 2
+            else:
+                stencil_adjoint_step(prop.ctx, prop.kappa, mc, mp, k - 1, rsrc, level(k), level(k - 1),
+                                     level(k - 2), grad)
+                state.reverse()
+                k -= 1
+
     if "levels" in ckpts:  # every level kept: no recompute
         L = ckpts["levels"]  # L[n + 1] = u^n
-        for k in range(nt, 0, -1):
-            stencil_adjoint_step(prop.ctx, prop.kappa, mu_cur, mu_prev, k - 1, rsrc, L[k + 1], L[k], L[k - 1], grad)
-            mu_cur, mu_prev = mu_prev, mu_cur
+        adjoint_range(nt, 0, lambda j: L[j + 1])
         return grad
     buf = torch.empty((C,) + tuple(prop.shape), device=prop.device)
     for n0 in sorted(ckpts, reverse=True):
@@ -115,11 +134,7 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
         for n in range(n0, n1):
             j = n - n0 + 1
             stencil_step_to(prop.ctx, prop.kappa, levels[j], levels[j - 1], levels[j + 1], n, src)
-        for k in range(n1, n0, -1):
-            j = k - n0 + 1  # levels[j] = u^k
-            stencil_adjoint_step(prop.ctx, prop.kappa, mu_cur, mu_prev, k - 1, rsrc,
-                                 levels[j], levels[j - 1], levels[j - 2], grad)
-            mu_cur, mu_prev = mu_prev, mu_cur
+        adjoint_range(n1, n0, lambda j, n0=n0, levels=levels: levels[j - n0 + 1])  # levels[j - n0 + 1] = u^j
     return grad
 
 

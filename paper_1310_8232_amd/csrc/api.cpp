@@ -1140,6 +1140,27 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
     return STENCIL_OK;
 }
 
+stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void *mu_km1, const void *u_k,
+                                 const void *u_km1, const void *u_km2, const void *u_km3, double *grad, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "the gradient needs FP32 storage");
+    if (!mu_k || !mu_km1 || !u_k || !u_km1 || !u_km2 || !u_km3 || !grad)
+        return fail(ctx, STENCIL_EINVAL, "null pointer");
+    const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+    const void *fields[] = {mu_k, mu_km1, u_k, u_km1, u_km2, u_km3};
+    for (const void *f : fields)
+        if (overlaps2(grad, gb, f, fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
+    hipError_t e = p1310::launch_grad2(grad, (const float *)mu_k, (const float *)mu_km1, (const float *)u_k,
+                                       (const float *)u_km1, (const float *)u_km2, (const float *)u_km3, npoints(ctx),
+                                       scale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
+    return STENCIL_OK;
+}
+
 stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
                               void *stream)
 {

@@ -274,3 +274,23 @@ def test_eight_point_tiles_for_16bit_storage():
             p.stencil_set_tile(ctx, eight[0])
         assert e.value.status == p.EUNSUPPORTED
         p.stencil_destroy(ctx)
+
+
+def test_gradient2_validation():
+    ctx = _init(nx=16, ny=16, nz=16)
+    n = 16 ** 3 * 4
+    base = 1 << 40
+    f = [base + i * 2 * n for i in range(6)]
+    g = base + 20 * n
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_gradient2(ctx, *f, f[3] + 8, stream=0)  # grad overlaps u^{k-1}
+    assert e.value.status == p.EALIAS
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_gradient2(ctx, f[0], 0, *f[2:], g, stream=0)
+    assert e.value.status == p.EINVAL
+    p.stencil_destroy(ctx)
+    ctx = _init(nx=16, ny=16, nz=16, storage="f16", storage_scale=1024.0)
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_gradient2(ctx, *f, g, stream=0)
+    assert e.value.status == p.EUNSUPPORTED
+    p.stencil_destroy(ctx)
