@@ -294,3 +294,14 @@ def test_gradient2_validation():
         p.stencil_gradient2(ctx, *f, g, stream=0)
     assert e.value.status == p.EUNSUPPORTED
     p.stencil_destroy(ctx)
+
+
+def test_c_program_links_and_checks_arguments():
+    # The C program that uses the ABI without Python: built by build(); with
+    # wrong arguments it exits with status 2 before touching the GPU.
+    import subprocess
+    exe = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c_abi", "_build", "plain_method")
+    if not os.path.exists(exe):
+        pytest.skip("C program not built")
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=30)
+    assert r.returncode == 2 and "usage" in r.stderr
