@@ -66,7 +66,7 @@ def test_two_step_bits_equal_one_step(R, shape):
     for t in p.stencil_list_tiles2(R, shape[0] % 4 == 0):
         for dz in (1, 7, 16, nz):
             for xcd in (1, 0):
-                tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, 1, dz, t.vw, xcd, t.pf))
+                tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, t.ry, dz, t.vw, xcd, t.pf))
     assert tiles
     for t in tiles:
         got = _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal=2, tile2=t)
