@@ -116,3 +116,35 @@ def test_run_in_segments_with_spare_list():
     ra, rb = prop.run(cuda(u0), cuda(um1), it, src, temporal=1)
     torch.cuda.synchronize()
     assert torch.equal(a, ra) and torch.equal(b, rb)
+
+
+def test_two_step_graph_capture_replays_match_eager():
+    # Three two-step launches and a closing one-step launch (7 steps)
+    # captured in one HIP graph on a side stream; each replay, with eager
+    # work in between, gives the bits of the eager run.
+    shape, R, nt = (64, 48, 40), 4, 7
+    v, dt, vmax, u0, um1, idx, amp = _case(shape, 77, R, nt)
+    log(f"case: two-step graph capture, {shape}, {nt} steps, 3 replays")
+    prop = p.Propagator(cuda(v), 10.0, dt, R, vmax=vmax)
+    src = p.make_src(cuda(idx, torch.int64), cuda(amp))
+    a0, b0 = cuda(u0), cuda(um1)
+    c, d = prop.zeros(), prop.zeros()
+    ea, eb = prop.run(a0.clone(), b0.clone(), nt, src, temporal=2, spare=(c, d))
+    torch.cuda.synchronize()
+    eager = (ea.clone(), eb.clone())
+    ga, gb, gc, gd = a0.clone(), b0.clone(), prop.zeros(), prop.zeros()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ra, rb = prop.run(ga, gb, nt, src, temporal=2, spare=(gc, gd))
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        ga.copy_(a0)
+        gb.copy_(b0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ra, eager[0]) and torch.equal(rb, eager[1]), f"replay {rep}"
+        _ = (ga * 2).sum().item()  # eager work between replays
