@@ -347,6 +347,15 @@ int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap);
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
                                     void *stream);
 
+/* Streaming reference in the one-step sweep's access order, without the
+ * stencil: out = (a + b) + c over [nz][ny][nx] FP32 fields (nx % 4 == 0,
+ * 16-byte aligned, out not overlapping an input: EINVAL / EALIAS), one
+ * workgroup per column of 256 x 4 points marching 256 planes, a cached and
+ * b, c, out non-temporal as in the sweep. The bandwidth ceiling of the
+ * sweep's own access pattern. Enqueued on `stream`. */
+stencil_status stencil_stream_probe_march(const void *a, const void *b, const void *c, void *out, int64_t nx,
+                                          int64_t ny, int64_t nz, void *stream);
+
 /* Message for a status code (static storage). */
 const char *stencil_strerror(stencil_status s);
 

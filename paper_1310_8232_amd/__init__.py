@@ -120,6 +120,7 @@ _sig = {
                               ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "stencil_pgrid": (_i32, [_i64, _i32, ctypes.POINTER(_i64), _i32]),
     "stencil_stream_probe": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp]),
+    "stencil_stream_probe_march": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp]),
     "stencil_strerror": (ctypes.c_char_p, [_i32]),
     "stencil_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -398,6 +399,13 @@ def stencil_pgrid(S: int, P: int):
 def stencil_stream_probe(a, b, c, out, nbytes: int, stream=None):
     """out = a (+ b) (+ c) over nbytes; b and c may be None."""
     _check(_lib.stencil_stream_probe(_ptr(a), _ptr(b), _ptr(c), _ptr(out), int(nbytes), _stream(stream)))
+
+
+def stencil_stream_probe_march(a, b, c, out, shape, stream=None):
+    """out = (a + b) + c over [nz, ny, nx] FP32 fields in the sweep's access order."""
+    nz, ny, nx = shape
+    _check(_lib.stencil_stream_probe_march(_ptr(a), _ptr(b), _ptr(c), _ptr(out), int(nx), int(ny), int(nz),
+                                           _stream(stream)))
 
 
 class Propagator:

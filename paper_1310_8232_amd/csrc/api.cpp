@@ -1488,4 +1488,16 @@ stencil_status stencil_stream_probe(const void *a, const void *b, const void *c,
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
 }
 
+stencil_status stencil_stream_probe_march(const void *a, const void *b, const void *c, void *out, int64_t nx,
+                                          int64_t ny, int64_t nz, void *stream)
+{
+    if (!a || !b || !c || !out || nx < 4 || nx % 4 || ny < 1 || nz < 1 || nx > 0x7fffffff || ny > 0x7fffffff ||
+        nz > 0x7fffffff || (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)out) & 15u))
+        return STENCIL_EINVAL;
+    const int64_t bytes = nx * ny * nz * 4;
+    if (overlaps(a, out, bytes) || overlaps(b, out, bytes) || overlaps(c, out, bytes)) return STENCIL_EALIAS;
+    hipError_t e = p1310::launch_stream_march(a, b, c, out, nx, ny, nz, (hipStream_t)stream);
+    return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
+}
+
 }  // extern "C"

@@ -262,6 +262,30 @@ __global__ void __launch_bounds__(256) stream_kernel(const f4 *a, const f4 *b, c
     }
 }
 
+// The same three-read, one-write stream in the one-step sweep's access order,
+// without the stencil: [nz][ny][nx] FP32 fields (nx % 4 == 0), a workgroup
+// of 64 x 4 threads owns a column of 64 four-float vectors x 4 rows and
+// marches kMarchDz planes; u^n-like input `a` cached, the others and the
+// output non-temporal, as in the sweep.
+constexpr int kMarchDz = 256;
+
+__global__ void __launch_bounds__(256) stream_march_kernel(const f4 *a, const f4 *b, const f4 *c, f4 *out, int nxv,
+                                                           int ny, int nz, int gx, int gy)
+{
+    const int blk = blockIdx.x;
+    const int x = (blk % gx) * 64 + (int)(threadIdx.x % 64);
+    const int y = ((blk / gx) % gy) * 4 + (int)(threadIdx.x / 64);
+    const int z0 = (blk / gx / gy) * kMarchDz;
+    const int z1 = (z0 + kMarchDz < nz) ? z0 + kMarchDz : nz;
+    if (x >= nxv || y >= ny) return;
+    const int64_t plane = (int64_t)nxv * ny;
+    for (int z = z0; z < z1; ++z) {
+        const int64_t i = z * plane + (int64_t)y * nxv + x;
+        const f4 v = (a[i] + __builtin_nontemporal_load(&b[i])) + __builtin_nontemporal_load(&c[i]);
+        __builtin_nontemporal_store(v, &out[i]);
+    }
+}
+
 // Same for any size and 4-byte alignment, one float per thread per step.
 template <int NIN>
 __global__ void __launch_bounds__(256) stream_kernel_scalar(const float *a, const float *b, const float *c, float *out,
@@ -433,6 +457,17 @@ hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, doub
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(kappa_kernel, dim3((unsigned)blocks), dim3(256), 0, s, v, kappa, n, dt, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_march(const void *a, const void *b, const void *c, void *out, int64_t nx, int64_t ny,
+                              int64_t nz, hipStream_t s)
+{
+    const int nxv = (int)(nx / 4);
+    const int64_t gx = (nxv + 63) / 64, gy = (ny + 3) / 4, gz = (nz + kMarchDz - 1) / kMarchDz;
+    if (gx * gy * gz > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_march_kernel, dim3((unsigned)(gx * gy * gz)), dim3(256), 0, s, (const f4 *)a,
+                       (const f4 *)b, (const f4 *)c, (f4 *)out, nxv, (int)ny, (int)nz, (int)gx, (int)gy);
     return hipGetLastError();
 }
 

@@ -305,3 +305,13 @@ def test_c_program_links_and_checks_arguments():
         pytest.skip("C program not built")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=30)
     assert r.returncode == 2 and "usage" in r.stderr
+
+
+def test_stream_probe_march_validation():
+    base = 1 << 40
+    n = 8 * 8 * 8 * 4
+    for args in ((base, base + n, base + 2 * n, base + 3 * n, 6, 8, 8),   # nx % 4
+                 (base, base + n, base + 2 * n, base + 3 * n + 4, 8, 8, 8),  # alignment
+                 (base, 0, base + 2 * n, base + 3 * n, 8, 8, 8)):  # null input
+        assert p._lib.stencil_stream_probe_march(*args, None) == p.EINVAL
+    assert p._lib.stencil_stream_probe_march(base, base + n, base + 2 * n, base + n + 16, 8, 8, 8, None) == p.EALIAS
