@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -258,6 +259,14 @@ bool zmarch_possible(const stencil_ctx *ctx)
     return (1 + 2 * ctx->R) * ctx->d.nx * ctx->d.ny * 4 < kWindowLimit;
 }
 
+// Deepest march whose window of dz + halo_planes planes stays below 2 GiB.
+int32_t max_dz(const stencil_ctx *ctx, int halo_planes)
+{
+    const int64_t plane_bytes = ctx->d.nx * ctx->d.ny * 4;
+    const int64_t dz = (kWindowLimit - 1) / plane_bytes - halo_planes;
+    return dz < 1 ? 0 : (int32_t)std::min<int64_t>(dz, 1 << 30);
+}
+
 stencil_tile default_tile(const stencil_ctx *ctx)
 {
     stencil_tile t = {};
@@ -286,7 +295,7 @@ stencil_tile default_tile(const stencil_ctx *ctx)
         t.ry = ctx->st == p1310::kF32 ? 2 : 1;
         t.vw = 1;
     }
-    t.dz = 64;
+    t.dz = std::min<int32_t>(64, max_dz(ctx, 2 * ctx->R));
     t.xcd = 1;
     t.pf = 0;
     return t;
@@ -306,7 +315,7 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
         t.vw = 1;
     }
     t.ry = 1;
-    t.dz = 128;
+    t.dz = std::min<int32_t>(128, max_dz(ctx, 4 * ctx->R));  // 0 (rejected) when no window fits
     t.xcd = 1;
     return t;
 }

@@ -315,3 +315,25 @@ def test_stream_probe_march_validation():
                  (base, 0, base + 2 * n, base + 3 * n, 8, 8, 8)):  # null input
         assert p._lib.stencil_stream_probe_march(*args, None) == p.EINVAL
     assert p._lib.stencil_stream_probe_march(base, base + n, base + 2 * n, base + n + 16, 8, 8, 8, None) == p.EALIAS
+
+
+def test_large_planes_fall_back_to_plain_tiling():
+    # A z-march window of dz + 2R planes must stay below 2 GiB: with
+    # 16384 x 16384 planes (1 GiB each) no z-march tile fits, the default is
+    # plain tiling, and z-march tiles are rejected with a clear message.
+    ctx = _init(nx=16384, ny=16384, nz=4)
+    t = p.stencil_get_tile(ctx)
+    assert t.kind == p.TILE_PLAIN
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, p.make_tile(p.TILE_ZMARCH, bx=64, by=4, ry=1, dz=1, vw=4))
+    assert e.value.status == p.EUNSUPPORTED and "2 GiB" in p.stencil_last_error(ctx)
+    p.stencil_destroy(ctx)
+    # 4096 x 4096 planes (64 MiB): dz + 8 planes fit up to dz = 23; the
+    # default tile takes that depth and deeper tiles are rejected.
+    ctx = _init(nx=4096, ny=4096, nz=64)
+    t = p.stencil_get_tile(ctx)
+    assert t.kind == p.TILE_ZMARCH and t.dz == 23
+    p.stencil_set_tile(ctx, p.make_tile(p.TILE_ZMARCH, bx=64, by=4, ry=1, dz=23, vw=4))
+    with pytest.raises(p.StencilError):
+        p.stencil_set_tile(ctx, p.make_tile(p.TILE_ZMARCH, bx=64, by=4, ry=1, dz=24, vw=4))
+    p.stencil_destroy(ctx)

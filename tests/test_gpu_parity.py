@@ -331,3 +331,28 @@ def test_stream_probe_sweep_order():
     p.stencil_stream_probe_march(a, b, c, out, shape)
     torch.cuda.synchronize()
     assert torch.equal(out, (a + b) + c)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("shape,kind", [((4096, 4096, 40), "zmarch"), ((16384, 16384, 2), "plain")])
+def test_largest_planes(shape, kind):
+    # Planes at the size limits: 4096^2 (64 MiB) takes the deepest z-march
+    # window below 2 GiB (dz + 2R = 31 planes); 16384^2 (1 GiB) fits no
+    # z-march window and runs plain tiling. Random fields, 3 steps, all
+    # points against the oracle.
+    nx, ny, nz = shape
+    log(f"case: largest planes {shape} ({kind}), 3 steps")
+    t0 = time.time()
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=17)
+    un, unm1, prop = gpu_run(v, 10.0, dt, vmax, 4, 3, u0, um1)
+    t = prop.tile.as_dict()
+    del prop
+    torch.cuda.empty_cache()
+    log(f"  tile {t} ({time.time() - t0:.0f}s)")
+    assert t["kind"] == (p.TILE_ZMARCH if kind == "zmarch" else p.TILE_PLAIN)
+    if kind == "zmarch":
+        assert t["dz"] == 23
+    ref_n, ref_nm1 = oracle_run(v, 10.0, dt, 4, 3, u0, um1)
+    log(f"  oracle ({time.time() - t0:.0f}s)")
+    assert_close(un, ref_n, what="u^3")
+    assert_close(unm1, ref_nm1, what="u^2")
