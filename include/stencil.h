@@ -48,7 +48,7 @@ typedef enum {
     STENCIL_EUNSTABLE = -2,     /* vmax*dt/h above the leapfrog stability limit */
     STENCIL_ENOMEM = -3,        /* host allocation failed */
     STENCIL_EDEVICE = -4,       /* a HIP call failed (message in stencil_last_error) */
-    STENCIL_EUNSUPPORTED = -5,  /* storage type or tile this build does not provide */
+    STENCIL_EUNSUPPORTED = -5,  /* storage type or tile the library has no compiled kernel for */
     STENCIL_EALIAS = -6         /* u_cur and u_prev_next overlap */
 } stencil_status;
 
@@ -296,7 +296,7 @@ stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out);
 stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out);
 
 /* Replace the current tile (a ZMARCH2 tile replaces the two-step tile);
- * rejects tiles this build cannot run on the context's grid (EUNSUPPORTED)
+ * rejects tiles the compiled kernels cannot run on the context's grid (EUNSUPPORTED)
  * without changing the current one. */
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
