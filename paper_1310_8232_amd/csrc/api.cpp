@@ -505,6 +505,9 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
         if (o.parts < 2) {
             // Every compiled tile shape x a list of z-march depths x XCD order on/off.
             std::vector<int64_t> dzs = {16, 32, 64, 128, 256};
+            // Short grids: more, shallower columns keep every CU busy.
+            if (d.nz <= 256) dzs.insert(dzs.begin(), 8);
+            if (d.nz <= 128) dzs.insert(dzs.begin(), 4);
             dzs.push_back(d.nz);
             for (const ZVariant *v : vars)
                 for (int64_t dz : dzs) {
