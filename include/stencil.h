@@ -15,8 +15,10 @@
  * paper's loop blocking (Section 3, Fig. 1(b)) becomes the workgroup tile;
  * its blocksize search (Sections 3.2-3.3, 3.6, 3.7) becomes stencil_tune.
  *
- * Data layout: every field is a contiguous FP32 array [nz][ny][nx] in device
- * memory, x unit-stride, point (z, y, x) at linear index (z*ny + y)*nx + x.
+ * Data layout: every field is a contiguous array [nz][ny][nx] in device
+ * memory, x unit-stride, point (z, y, x) at linear index (z*ny + y)*nx + x;
+ * kappa and the gradient fields are FP32 / FP64, wavefields are in the
+ * context's storage type (FP32 unless FP16/BF16 is chosen).
  *
  * Ownership: field pointers are borrowed device memory (e.g. torch tensors);
  * the library never allocates, frees or retains them. A context owns only
@@ -29,9 +31,12 @@
  * stencil_last_error. No C++ exception crosses this interface.
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
- * stream). stencil_kappa and stencil_step only enqueue work: no allocation,
- * no synchronisation, no host read of device memory, so they may be captured
- * in a HIP graph.
+ * stream). The stepping calls (stencil_kappa, stencil_step, stencil_step_to,
+ * stencil_step2, stencil_adjoint_step, stencil_gradient2, stencil_sample,
+ * stencil_misfit, stencil_convert, stencil_batch_step) only enqueue work: no
+ * allocation, no synchronisation, no host read of device memory, so they may
+ * be captured in a HIP graph. stencil_tune and stencil_batch_tune synchronise
+ * the stream.
  */
 #ifndef PAPER_1310_8232_AMD_STENCIL_H
 #define PAPER_1310_8232_AMD_STENCIL_H
@@ -49,7 +54,7 @@ typedef enum {
     STENCIL_ENOMEM = -3,        /* host allocation failed */
     STENCIL_EDEVICE = -4,       /* a HIP call failed (message in stencil_last_error) */
     STENCIL_EUNSUPPORTED = -5,  /* storage type or tile the library has no compiled kernel for */
-    STENCIL_EALIAS = -6         /* u_cur and u_prev_next overlap */
+    STENCIL_EALIAS = -6         /* fields that must be distinct overlap (e.g. u_cur and the output) */
 } stencil_status;
 
 typedef struct stencil_ctx stencil_ctx;  /* opaque */
