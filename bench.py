@@ -417,10 +417,15 @@ def paper_bench(args) -> int:
 
         key = f"{nx}x{ny}x{nz}"
         rec = {}
-        rep, _, _ = prop.tune(n_iter=args.tune_iter, n_rep=1, parts=0, include_plain=True)
+        rep, tab, cands = prop.tune(n_iter=args.tune_iter, n_rep=1, parts=0, include_plain=True, table_cap=2048)
         best = total_ms()
+        # The whole exhaustive table (the GPU form of the paper's blocksize
+        # landscapes, Figs. 3-4): Gpt/s of every candidate over n_iter steps.
+        npts = nx * ny * nz
+        landscape = [{"tile": t, "gpts": round(npts * args.tune_iter / (ms * 1e-3) / 1e9, 2)}
+                     for t, ms in zip(cands or [], (tab or [[]])[0])]
         rec["exhaustive"] = {"n_candidates": rep["n_candidates"], "tile": rep["tile"], "seconds": rep["seconds"],
-                             "total_ms_448": round(best, 3)}
+                             "total_ms_448": round(best, 3), "landscape": landscape}
         pol = {}
         for policy in ("ob", "min", "worst", "avg"):
             runs = []
