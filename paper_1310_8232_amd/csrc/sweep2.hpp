@@ -224,15 +224,21 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
             if (zq + 1 >= z0 && zq + 1 < z1)
                 k2[(j + 1) & 1] = bload<VW, 0>(rk, skoff, (uint32_t)(zq + 1 - zlo) * kbytes);
 
-            // Step 2: u^{n+2}(z') on the own tile.
-            if (st2 && own) {
+            // Step 2: u^{n+2}(z') on the own tile. Every lane runs it in every
+            // iteration (no divergent branch, so the compiler schedules it
+            // together with step 1): ring lanes read the LDS taps of the
+            // nearest own position and planes outside the chunk compute on
+            // stale LDS data; neither is stored (the store offset is out of
+            // the window for them).
+            {
+                const int tyc = min(max(ty, R), BY - R - 1), txc = min(max(tx, HV), BX - HV - 1);
                 V yv[2 * R];
 #pragma unroll
                 for (int d = 0; d < R; ++d) {
-                    yv[d] = *reinterpret_cast<const V *>(buf2 + (ty - R + d) * EX + tx * VW);
-                    yv[R + d] = *reinterpret_cast<const V *>(buf2 + (ty + 1 + d) * EX + tx * VW);
+                    yv[d] = *reinterpret_cast<const V *>(buf2 + (tyc - R + d) * EX + txc * VW);
+                    yv[R + d] = *reinterpret_cast<const V *>(buf2 + (tyc + 1 + d) * EX + txc * VW);
                 }
-                const float *row = buf2 + ty * EX + tx * VW - HX;
+                const float *row = buf2 + tyc * EX + txc * VW - HX;
                 V xl[HV], xr[HV];
 #pragma unroll
                 for (int v = 0; v < HV; ++v) {
@@ -266,7 +272,7 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
                     for (int e = 0; e < VW; ++e)
                         if (e == s_e) out.a[e] = __builtin_fmaf(kq.a[e], s_amp2, out.a[e]);
                 }
-                ustore<ST, VW, kNT>(out, rn2, soff, (uint32_t)(zq - zlo) * pbytes);
+                ustore<ST, VW, kNT>(out, rn2, st2 ? soff : kOOB, st2 ? (uint32_t)(zq - zlo) * pbytes : 0u);
             }
 
             // Step 1: u^{n+1}(z) on E.
