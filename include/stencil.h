@@ -176,7 +176,8 @@ stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *
  * and u^{it+2} to u_next2, with the sources of steps it and it+1. The four
  * wavefields must be distinct and must not overlap (EALIAS): the inputs are
  * read around every tile by its neighbours while the outputs are written.
- * At most one source (EUNSUPPORTED otherwise); it+1 < src->nt (EINVAL).
+ * At most one source (EUNSUPPORTED otherwise; a negative count is EINVAL);
+ * it+1 < src->nt (EINVAL).
  * Results are bit-identical to two stencil_step calls. Uses the context's
  * two-step tile; FP32 storage. Capture-safe. */
 stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
@@ -256,8 +257,10 @@ typedef struct {
  * Copies each context's current tile; allocates one small device table
  * (hipMalloc, here only). Buffers alternate: at step `it` with
  * (it - it0) even, u_a holds u^{it}, u_b holds u^{it-1} and receives u^{it+1};
- * with (it - it0) odd the roles swap. Rejects a null or aliased shot (EINVAL /
- * EALIAS) and mixed devices. */
+ * with (it - it0) odd the roles swap. Rejects (EINVAL / EALIAS) a null shot,
+ * a shot whose buffers overlap each other or its kappa, a buffer that overlaps
+ * any field of another shot (shots may share one kappa, which is only read),
+ * and mixed devices. */
 stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out);
 
 /* One step of every shot of the batch on `stream`; capture-safe (no
@@ -301,8 +304,10 @@ stencil_status stencil_get_tile(const stencil_ctx *ctx, stencil_tile *out);
 stencil_status stencil_get_tile2(const stencil_ctx *ctx, stencil_tile *out);
 
 /* Replace the current tile (a ZMARCH2 tile replaces the two-step tile);
- * rejects tiles the compiled kernels cannot run on the context's grid (EUNSUPPORTED)
- * without changing the current one. */
+ * rejects tiles the compiled kernels cannot run on the context's grid
+ * (EUNSUPPORTED) without changing the current one: no compiled kernel for the
+ * shape, vw not dividing nx, a z window of 2 GiB or more, or a launch of more
+ * than 2^31-1 workgroups or 2^32-1 work-items. */
 stencil_status stencil_set_tile(stencil_ctx *ctx, const stencil_tile *tile);
 
 /* Compiled ZMARCH tiles for a radius and storage type, with vw = 4

@@ -64,6 +64,13 @@ namespace {
 constexpr int kXcds = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
 constexpr int64_t kWindowLimit = (int64_t)1 << 31;
 
+// A 1-D launch: at most 2^31 - 1 workgroups and 2^32 - 1 work-items (the
+// dispatch packet's grid size is a 32-bit count of work-items).
+bool launch_fits(int64_t blocks, int threads)
+{
+    return blocks >= 1 && blocks <= 0x7fffffff && blocks * threads <= (int64_t)0xffffffff;
+}
+
 // ---------------------------------------------------------------------------
 // Exact rational weights of the order-2R central second difference.
 // c_m = 2 (-1)^{m+1} (R!)^2 / (m^2 (R-m)! (R+m)!), c_0 = -2 sum c_m.
@@ -230,7 +237,8 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
         if ((t.dz + 4 * ctx->R) * d.nx * d.ny * 4 >= kWindowLimit)
             return fail(ctx, STENCIL_EUNSUPPORTED, "two-step window (dz + 4R planes) must stay below 2 GiB; lower dz");
         const int64_t gx = (d.nx + v->own_x - 1) / v->own_x, gy = (d.ny + v->own_y - 1) / v->own_y;
-        if (gx * gy * ((d.nz + t.dz - 1) / t.dz) > 0x7fffffff) return fail(ctx, STENCIL_EUNSUPPORTED, "too many workgroups");
+        if (!launch_fits(gx * gy * ((d.nz + t.dz - 1) / t.dz), v->threads))
+            return fail(ctx, STENCIL_EUNSUPPORTED, "launch too large (over 2^31-1 workgroups or 2^32-1 work-items); raise dz");
         t.xcd = t.xcd ? kXcds : 0;
         *norm = t;
         return STENCIL_OK;
@@ -238,8 +246,8 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     if (t.kind != STENCIL_TILE_ZMARCH) return fail(ctx, STENCIL_EUNSUPPORTED, "unknown tile kind");
     if (t.vw == 0) t.vw = auto_vw(ctx);
     if (t.vw < 1 || d.nx % t.vw) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx");
-    if (!find_variant(ctx, t))
-        return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
+    const ZVariant *zv = find_variant(ctx, t);
+    if (!zv) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
     if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
     if (t.dz > d.nz) t.dz = (int32_t)d.nz;
     const int64_t plane_bytes = d.nx * d.ny * 4;
@@ -248,7 +256,8 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     const int64_t gx = (d.nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw);
     const int64_t gy = (d.ny + (int64_t)t.by * t.ry - 1) / ((int64_t)t.by * t.ry);
     const int64_t gz = (d.nz + t.dz - 1) / t.dz;
-    if (gx * gy * gz > 0x7fffffff) return fail(ctx, STENCIL_EUNSUPPORTED, "too many workgroups");
+    if (!launch_fits(gx * gy * gz, zv->threads))
+        return fail(ctx, STENCIL_EUNSUPPORTED, "launch too large (over 2^31-1 workgroups or 2^32-1 work-items); raise dz");
     t.xcd = t.xcd ? kXcds : 0;
     *norm = t;
     return STENCIL_OK;
@@ -814,6 +823,7 @@ stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_
     if (!vec_aligned(ctx, ctx->tile2.vw, kappa, {u_cur, u_prev, u_next, u_next2}))
         return fail(ctx, STENCIL_EINVAL, "kappa must be 4*vw-byte and the wavefields vw-value aligned");
     if (src && src->n != 0) {
+        if (src->n < 0) return fail(ctx, STENCIL_EINVAL, "bad source description");
         if (src->n > 1) return fail(ctx, STENCIL_EUNSUPPORTED, "two-step launches take at most one source");
         if (!src->idx || !src->amp) return fail(ctx, STENCIL_EINVAL, "bad source description");
         if (it < 0 || it + 1 >= src->nt) return fail(ctx, STENCIL_EINVAL, "steps it and it+1 need source samples");
@@ -1214,6 +1224,22 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             delete bt;
             return STENCIL_EINVAL;
         }
+        // One launch sweeps every shot: a buffer that one shot writes must not
+        // overlap any field of another (kappa may be shared: it is only read).
+        for (int j = 0; j < i; ++j) {
+            const stencil_shot &o = shots[j];
+            const int64_t oub = npoints(o.ctx) * o.ctx->es, okb = npoints(o.ctx) * 4;
+            const void *mine[] = {sh.u_a, sh.u_b}, *theirs[] = {o.u_a, o.u_b};
+            bool clash = false;
+            for (const void *w : mine)
+                clash = clash || overlaps2(w, ub, o.u_a, oub) || overlaps2(w, ub, o.u_b, oub) ||
+                        overlaps2(w, ub, o.kappa, okb);
+            for (const void *w : theirs) clash = clash || overlaps2(w, oub, sh.kappa, kb);
+            if (clash) {
+                delete bt;
+                return STENCIL_EALIAS;
+            }
+        }
         if (sh.src.n > 0) bt->nt_min = std::min(bt->nt_min, sh.src.nt);
         bt->shots.push_back({sh.ctx, (const float *)sh.kappa, sh.u_a, sh.u_b, sh.src,
                              tiles ? tiles[i] : sh.ctx->tile});
@@ -1274,7 +1300,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             t0.push_back(e);
             t1.push_back(o);
         }
-        if (blocks > 0x7fffffff) {
+        if (!launch_fits(blocks, g.v->threads)) {
             delete bt;
             return STENCIL_EUNSUPPORTED;
         }
@@ -1392,6 +1418,13 @@ stencil_status stencil_batch_tune(const stencil_shot *shots, int32_t n, const st
     // Timing copies of the shots without sources.
     std::vector<stencil_shot> quiet(shots, shots + n);
     for (auto &q : quiet) q.src = stencil_src{};
+    {
+        // The shots as given must form a batch (no null or aliased fields).
+        stencil_batch *probe = nullptr;
+        const stencil_status st = build_batch(quiet.data(), n, nullptr, 0, &probe);
+        if (st != STENCIL_OK) return fail(nullptr, st, "the shots do not form a batch (null, aliased or mixed devices)");
+        stencil_batch_destroy(probe);
+    }
     // Candidates: those of the first shot that every shot can run.
     std::vector<stencil_tile> base = make_candidates(shots[0].ctx, o);
     std::vector<std::vector<stencil_tile>> cands;  // per candidate: one tile per shot

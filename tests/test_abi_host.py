@@ -348,3 +348,73 @@ def test_make_src_validates_and_keeps_its_tensors():
     src = p.StencilSrc(0, None, None, 0)
     src._keep = ("idx", "amp")
     assert src._keep == ("idx", "amp")
+
+
+def test_launch_size_limits():
+    # 4096 x 4096 x 300 (5e9 points): a one-point-per-thread tile marching one
+    # plane per workgroup would need over 2^32 work-items, which one dispatch
+    # cannot hold; two rows per thread (or a deeper march) fits.
+    ctx = _init(nx=4096, ny=4096, nz=300)
+    one_row = [t for t in p.stencil_list_tiles(4, False) if t.ry == 1]
+    two_rows = [t for t in p.stencil_list_tiles(4, False) if t.ry == 2]
+    assert one_row and two_rows
+    t = one_row[0]
+    t.dz = 1
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, t)
+    assert e.value.status == p.EUNSUPPORTED and "work-items" in p.stencil_last_error(ctx)
+    t.dz = 2
+    p.stencil_set_tile(ctx, t)
+    t = two_rows[0]
+    t.dz = 1
+    p.stencil_set_tile(ctx, t)
+    # The two-step kernel with one point per thread: 24 x 8 own points per
+    # 512-thread workgroup.
+    t2 = [t for t in p.stencil_list_tiles2(4, False)][0]
+    t2.dz = 1
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, t2)
+    assert e.value.status == p.EUNSUPPORTED
+    t2.dz = 8
+    p.stencil_set_tile(ctx, t2)
+    p.stencil_destroy(ctx)
+
+
+def test_step2_rejects_negative_source_count():
+    ctx = _init(nx=64, ny=48, nz=40)
+    n = 64 * 48 * 40 * 4
+    base = 1 << 40
+    k, a, b, c, d = (base + i * 2 * n for i in range(5))
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step2(ctx, k, a, b, c, d, 0, p.StencilSrc(-1, base + 64 * n, base + 65 * n, 10), 0)
+    assert e.value.status == p.EINVAL
+    p.stencil_destroy(ctx)
+
+
+def test_batch_rejects_buffers_shared_between_shots():
+    # Fake device pointers: validation happens before any HIP call, and with
+    # plain tiles a batch holds no device table, so even a valid batch is
+    # created and destroyed on the CPU.
+    ctxs = [_init(nx=32, ny=32, nz=32) for _ in range(2)]
+    for c in ctxs:
+        p.stencil_set_tile(c, p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1))
+    n = 32 ** 3 * 4
+    base = 1 << 40
+    f = [base + i * 2 * n for i in range(8)]
+    ok = [(ctxs[0], f[0], f[1], f[2], None), (ctxs[1], f[0], f[3], f[4], None)]  # one kappa for both
+    p.stencil_batch_destroy(p.stencil_batch_create(ok))
+    bad = [
+        [(ctxs[0], f[0], f[1], f[2], None), (ctxs[1], f[5], f[2], f[4], None)],           # same u buffer
+        [(ctxs[0], f[0], f[1], f[2], None), (ctxs[1], f[5], f[3], f[1] + 64, None)],      # partial overlap
+        [(ctxs[0], f[0], f[1], f[2], None), (ctxs[1], f[1], f[3], f[4], None)],           # kappa is another's u
+        [(ctxs[0], f[5], f[1], f[2], None), (ctxs[1], f[0], f[5] + 256, f[4], None)],     # u is another's kappa
+    ]
+    for shots in bad:
+        with pytest.raises(p.StencilError) as e:
+            p.stencil_batch_create(shots)
+        assert e.value.status == p.EALIAS
+        with pytest.raises(p.StencilError) as e:
+            p.stencil_batch_tune(shots, stream=0)
+        assert e.value.status == p.EALIAS
+    for c in ctxs:
+        p.stencil_destroy(c)
