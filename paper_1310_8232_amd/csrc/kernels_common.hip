@@ -77,22 +77,92 @@ __global__ void __launch_bounds__(256) kappa_m_kernel(const float *m, float *kap
 
 // Several point sources, one thread per source. Repeated indices are added
 // by the thread of their first occurrence, in index order, so the result is
-// the same as adding the sources one after another.
+// the same as adding the sources one after another. Finding repeats: every
+// workgroup walks the index list in chunks of kInjectChunk and builds, in
+// LDS, a hash table (linear probing) from grid index to the first and last
+// source number and the number of occurrences in the chunk; each thread then
+// looks up its own index. A chunk before the thread's own that holds the
+// index, or a first occurrence before the thread in its own chunk, makes an
+// earlier thread the owner. The owner adds its chunk's occurrences and those
+// of later chunks in order: the one or two positions the table names, or a
+// scan from the first to the last when a chunk holds the index three or more
+// times. Cost: O(n / 256) LDS atomics per thread and chunk, instead of the
+// O(n) dependent reads of a direct search.
+constexpr int kInjectChunk = 1024;               // source indices per chunk
+constexpr int kInjectSlots = 2 * kInjectChunk;   // hash table capacity (power of two)
+
+__device__ __forceinline__ uint32_t inject_slot(uint64_t q, uint32_t mask)
+{
+    return (uint32_t)((q * 0x9E3779B97F4A7C15ull) >> 40) & mask;  // Fibonacci hashing
+}
+
 template <typename ST>
 __global__ void __launch_bounds__(256) inject_kernel(ST *u, const float *kappa, int64_t n_points, const int64_t *idx,
                                                      const float *amp, int nsrc, int64_t it, float scale)
 {
+    __shared__ unsigned long long keys[kInjectSlots];
+    __shared__ int kfirst[kInjectSlots], klast[kInjectSlots], kcount[kInjectSlots];
+    const unsigned long long kEmpty = ~0ull;  // no grid index (they are >= 0)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nsrc) return;
-    const int64_t p = idx[j];
-    if (p < 0 || p >= n_points) return;
-    for (int k = 0; k < j; ++k)
-        if (idx[k] == p) return;  // an earlier source owns this point
-    const float kp = kappa[p];
-    float v = (float)u[p];
-    for (int k = j; k < nsrc; ++k)
-        if (idx[k] == p) v = __builtin_fmaf(kp, amp[it * nsrc + k] * scale, v);
-    u[p] = (ST)v;
+    const int64_t p = j < nsrc ? idx[j] : -1;
+    bool owner = p >= 0 && p < n_points;
+    float kp = 0.0f, v = 0.0f;
+    if (owner) {
+        kp = kappa[p];
+        v = (float)u[p];
+    }
+    const float *row = amp + it * nsrc;
+    for (int c0 = 0; c0 < nsrc; c0 += kInjectChunk) {
+        const int cn = min(kInjectChunk, nsrc - c0);
+        int H = 64;
+        while (H < 2 * cn) H *= 2;
+        const uint32_t mask = (uint32_t)H - 1;
+        __syncthreads();  // the previous chunk's lookups are done
+        for (int s = threadIdx.x; s < H; s += blockDim.x) {
+            keys[s] = kEmpty;
+            kfirst[s] = 0x7fffffff;
+            klast[s] = -1;
+            kcount[s] = 0;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < cn; t += blockDim.x) {
+            const int64_t q = idx[c0 + t];
+            if (q < 0 || q >= n_points) continue;
+            uint32_t h = inject_slot((uint64_t)q, mask);
+            for (int probe = 0; probe < H; ++probe) {  // H >= 2 cn: a free slot exists
+                const unsigned long long prev = atomicCAS(&keys[h], kEmpty, (unsigned long long)q);
+                if (prev == kEmpty || prev == (unsigned long long)q) {
+                    atomicMin(&kfirst[h], c0 + t);
+                    atomicMax(&klast[h], c0 + t);
+                    atomicAdd(&kcount[h], 1);
+                    break;
+                }
+                h = (h + 1) & mask;
+            }
+        }
+        __syncthreads();
+        if (!owner) continue;
+        uint32_t h = inject_slot((uint64_t)p, mask);
+        for (int probe = 0; probe < H; ++probe) {
+            const unsigned long long kq = keys[h];
+            if (kq == kEmpty) break;  // p does not occur in this chunk
+            if (kq == (unsigned long long)p) {
+                const int f = kfirst[h], l = klast[h], c = kcount[h];
+                if (f < j) {
+                    owner = false;  // an earlier source holds this point
+                } else if (c <= 2) {
+                    v = __builtin_fmaf(kp, row[f] * scale, v);
+                    if (l != f) v = __builtin_fmaf(kp, row[l] * scale, v);
+                } else {
+                    for (int k = f; k <= l; ++k)
+                        if (idx[k] == p) v = __builtin_fmaf(kp, row[k] * scale, v);
+                }
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+    if (owner) u[p] = (ST)v;
 }
 
 // FP32 field <-> storage: to storage dst = round(src * scale) (nearest even),

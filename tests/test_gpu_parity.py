@@ -175,6 +175,40 @@ def test_several_sources_and_out_of_range_index():
     assert_close(unm1, ref_nm1, what="u^n-1")
 
 
+def test_many_sources_with_repeats_across_blocks_and_chunks():
+    # 2600 sources: the injection kernel runs 11 workgroups of 256 threads and
+    # scans the index list in three LDS chunks of 1024. Repeats sit inside a
+    # workgroup, across workgroups, across a chunk boundary and at the two ends
+    # of the list; two indices are outside the grid. From rest the sweep gives
+    # exactly 0, and with kappa = 1/16 (v dt / h = 1/4) and amplitudes in
+    # multiples of 1/8 every sum is exact, so the field must equal the plain
+    # sum of kappa * amp per point bit for bit.
+    nx, ny, nz = 64, 48, 40
+    n = nx * ny * nz
+    v = np.full((nz, ny, nx), 2048.0, np.float32)
+    h, dt = 8.0, 1.0 / 1024.0
+    rng = np.random.default_rng(workloads.SEED + 61)
+    nsrc, nt, it = 2600, 5, 3
+    idx = rng.integers(0, n, nsrc).astype(np.int64)
+    for a, b in ((3, 17), (5, 700), (1023, 1024), (40, 2047), (0, nsrc - 1), (2048, 2599), (100, 1500)):
+        idx[b] = idx[a]
+    idx[9], idx[1030] = n + 3, -1
+    amp = (rng.integers(-64, 65, (nt, nsrc)) / 8.0).astype(np.float32)
+    log(f"case: {nsrc} sources with repeats, step it={it} from rest, exact arithmetic")
+    prop = p.Propagator(cuda(v), h, dt, 4, vmax=2048.0)
+    src = p.make_src(cuda(idx, torch.int64), cuda(amp))
+    a, b = prop.zeros(), prop.zeros()
+    prop.step(a, b, it, src)
+    torch.cuda.synchronize()
+    ref = np.zeros(n, np.float64)
+    for k in range(nsrc):
+        if 0 <= idx[k] < n:
+            ref[idx[k]] += 0.0625 * float(amp[it, k])
+    got = b.cpu().numpy().reshape(-1).astype(np.float64)
+    assert np.array_equal(got, ref)
+    assert a.abs().max().item() == 0.0
+
+
 def test_tune_selection_follows_rule_and_cache(tmp_path):
     nx, ny, nz = 96, 64, 48
     v, dt, vmax, _, _ = _random_case(nx, ny, nz, seed=31)
