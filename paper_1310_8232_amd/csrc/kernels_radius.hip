@@ -28,7 +28,8 @@ namespace p1310 {
 #define ZV(BX, BY, RY, VW, PF) ZVS(BX, BY, RY, VW, PF, kF32)
 
 // 16-bit wavefield storage (radii 4 and 5): four- and eight-point vectors (an
-// eight-point vector of 16-bit values is one 16-byte access), one-point rows.
+// eight-point vector of 16-bit values is one 16-byte access), one-point rows,
+// and tiles of 16 and 32 rows (less y halo per point).
 #if RADIUS >= 4
 #define ZV16(STT)                                                                                \
     ZVS(16, 8, 1, 4, 0, STT) ZVS(16, 8, 2, 4, 0, STT) ZVS(32, 8, 1, 4, 0, STT)                  \
@@ -36,7 +37,9 @@ namespace p1310 {
     ZVS(16, 16, 1, 4, 0, STT) ZVS(64, 4, 1, 4, 1, STT) ZVS(64, 4, 1, 1, 0, STT)                  \
     ZVS(128, 2, 1, 4, 0, STT) ZVS(32, 16, 1, 4, 0, STT) ZVS(64, 8, 1, 4, 0, STT)                 \
     ZVS(16, 8, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 0, STT) ZVS(32, 4, 1, 8, 0, STT)                   \
-    ZVS(64, 4, 1, 8, 0, STT) ZVS(16, 16, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 1, STT)
+    ZVS(64, 4, 1, 8, 0, STT) ZVS(16, 16, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 1, STT)                  \
+    ZVS(32, 16, 2, 4, 0, STT) ZVS(16, 16, 2, 4, 0, STT) ZVS(32, 8, 2, 4, 0, STT)                 \
+    ZVS(64, 8, 2, 4, 0, STT)
 #else
 #define ZV16(STT)
 #endif
@@ -49,6 +52,7 @@ static const ZVariant kTable[] = {
     ZV(32, 8, 1, 4, 0) ZV(32, 8, 2, 4, 0)
     ZV(64, 2, 2, 4, 0) ZV(64, 4, 1, 4, 0) ZV(64, 4, 2, 4, 0)
     ZV(64, 2, 1, 4, 0) ZV(64, 8, 1, 4, 0) ZV(32, 16, 1, 4, 0) ZV(128, 2, 1, 4, 0) ZV(128, 4, 1, 4, 0)
+    ZV(32, 16, 2, 4, 0) ZV(64, 8, 2, 4, 0)
     ZV(64, 8, 1, 4, 1) ZV(128, 2, 1, 4, 1)
     ZV(16, 4, 2, 4, 1) ZV(16, 8, 1, 4, 1) ZV(16, 8, 2, 4, 1) ZV(16, 16, 1, 4, 1)
     ZV(32, 4, 2, 4, 1) ZV(32, 8, 1, 4, 1) ZV(64, 4, 1, 4, 1)
