@@ -103,8 +103,10 @@ typedef struct {
 
 /* Point sources (all device memory, borrowed): idx[n] linear indices,
  * amp[nt][n] samples; step `it` adds kappa(idx[j]) * amp[it*n + j] to
- * u^{it+1}(idx[j]) for j = 0..n-1 in order. Indices outside the grid are
- * skipped by the kernels. */
+ * u^{it+1}(idx[j]) for j = 0..n-1 in order (an index may repeat; its terms
+ * are added in that order). Indices outside the grid are skipped by the
+ * kernels. One source is added inside the sweep; n > 1 costs one more launch
+ * per step in which every workgroup of 256 sources reads all n indices once. */
 typedef struct {
     int32_t n;
     const int64_t *idx;
