@@ -474,7 +474,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-two-step", action="store_true", help="search one-step tiles only")
-    ap.add_argument("--paper-repeats", type=int, default=5, help="searches per policy (paper workload)")
+    ap.add_argument("--paper-repeats", type=int, default=10, help="searches per policy (paper workload; the paper reports 10 executions)")
     ap.add_argument("--paper-shapes", type=str, default="", help="e.g. 200x200x800,300x300x800")
     ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision", "paper"), default="sweep",
                     help="sweep: the autotuned step (default); gradient: misfit + adjoint gradient; "
