@@ -2,6 +2,7 @@
 // compiler command line; the library links one object per radius).
 #include "sweep.hpp"
 #include "sweep2.hpp"
+#include "sweep_batch.hpp"
 
 #ifndef RADIUS
 #error "compile with -DRADIUS=<3|4|5>"

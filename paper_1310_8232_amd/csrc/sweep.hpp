@@ -430,22 +430,6 @@ __global__ void __launch_bounds__(BX * BY) zmarch_kernel(SweepArgs a)
     zmarch_body<R, BX, BY, RY, VW, PF, ST>(a, b);
 }
 
-// Several grids (shots) in one launch: the launch grid concatenates every
-// shot's workgroups; wg_begin[s] is the first workgroup of shot s. Each shot
-// keeps its own sizes, march depth, fields and source; `it` is the step.
-template <int R, int BX, int BY, int RY, int VW, int PF, typename ST>
-__global__ void __launch_bounds__(BX * BY) zmarch_batch_kernel(const SweepArgs *shots, const int *wg_begin,
-                                                               int nshots, int xcd, int64_t it)
-{
-    int b = blockIdx.x;
-    if (xcd > 1) b = xcd_order(b, gridDim.x, xcd);
-    int s = 0;
-    while (s + 1 < nshots && wg_begin[s + 1] <= b) ++s;
-    SweepArgs a = shots[s];
-    a.it = it;
-    zmarch_body<R, BX, BY, RY, VW, PF, ST>(a, b - wg_begin[s]);
-}
-
 // ---------------------------------------------------------------------------
 // Plain tiling: one thread per point, a bx x by x bz workgroup per block of
 // the grid, every tap read from memory (caches only). Same arithmetic order.
