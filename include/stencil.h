@@ -151,7 +151,12 @@ typedef struct {
 
 /* Create a context. Validates sizes, radius, storage, h, dt, vmax (> 0) and
  * the stability limit vmax*dt/h <= stencil_cfl_limit(radius) (EUNSTABLE).
- * Host-only: no HIP call. *out is set only on success. */
+ * Host-only: no HIP call. *out is set only on success.
+ * Environment: STENCIL_TUNE_CACHE names a tune cache file whose last entry
+ * for this grid, radius and storage gives the initial tile when d->tile is
+ * kind 0 (unreadable lines and tiles no kernel runs are ignored: built-in
+ * default); STENCIL_LOG (anything but empty or "0") prints one line to stderr
+ * per context created and per search (stencil_tune, stencil_batch_tune). */
 stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out);
 
 /* Release a context (NULL is ignored). */

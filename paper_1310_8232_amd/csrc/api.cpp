@@ -143,6 +143,29 @@ double cfl_limit_of(int R)
 // Last error of calls made without a context (batches, misfit, probe), per thread.
 thread_local std::string g_err;
 
+// STENCIL_LOG set to anything but "" or "0": one line per context creation
+// and per search on stderr (read at each such call, never in a step).
+bool log_on()
+{
+    const char *e = std::getenv("STENCIL_LOG");
+    return e && *e && std::strcmp(e, "0") != 0;
+}
+
+const char *storage_name(int st)
+{
+    static const char *kst[] = {"f32", "f16", "bf16"};
+    return (st >= 0 && st <= 2) ? kst[st] : "?";
+}
+
+std::string tile_text(const stencil_tile &t)
+{
+    char b[160];
+    static const char *kind[] = {"auto", "plain", "zmarch", "zmarch2"};
+    std::snprintf(b, sizeof b, "%s %dx%d ry%d dz%d vw%d xcd%d pf%d", (t.kind >= 0 && t.kind <= 3) ? kind[t.kind] : "?",
+                  t.bx, t.by, t.ry, t.dz, t.vw, t.xcd, t.pf);
+    return b;
+}
+
 stencil_status fail(stencil_ctx *ctx, stencil_status st, const std::string &msg)
 {
     if (ctx) ctx->err = msg;
@@ -732,17 +755,24 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     ctx->scale = (float)scale;
     stencil_coefficients(ctx->R, ctx->cf);
     stencil_tile t = default_tile(ctx);
+    const char *origin = "default";
     if (d->tile.kind != STENCIL_TILE_AUTO) {
         t = d->tile;
+        origin = "given";
     } else {
         double mn, act;
         stencil_tile c;
-        if (cache_lookup(std::getenv("STENCIL_TUNE_CACHE"), ctx, false, &c, &mn, &act)) t = c;
+        if (cache_lookup(std::getenv("STENCIL_TUNE_CACHE"), ctx, false, &c, &mn, &act)) {
+            t = c;
+            origin = "tune cache";
+        }
     }
     stencil_tile norm;
     stencil_status st = check_tile(ctx, t, &norm);
-    if (st != STENCIL_OK && d->tile.kind == STENCIL_TILE_AUTO)
+    if (st != STENCIL_OK && d->tile.kind == STENCIL_TILE_AUTO) {
         st = check_tile(ctx, default_tile(ctx), &norm);  // bad cache entry: fall back
+        origin = "default (the tune cache entry is not runnable)";
+    }
     if (st != STENCIL_OK) {
         delete ctx;
         return st;
@@ -750,6 +780,10 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     ctx->tile = norm;
     if (check_tile(ctx, default_tile2(ctx), &norm) == STENCIL_OK) ctx->tile2 = norm;
     ctx->err.clear();
+    if (log_on())
+        std::fprintf(stderr, "stencil: init %lldx%lldx%lld R%d %s device %d, tile %s (%s)\n", (long long)d->nx,
+                     (long long)d->ny, (long long)d->nz, ctx->R, storage_name(ctx->st), d->device,
+                     tile_text(ctx->tile).c_str(), origin);
     *out = ctx;
     return STENCIL_OK;
 }
@@ -1029,6 +1063,10 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
                 report->gap = (act - mn) / mn;
                 report->from_cache = 1;
                 report->n_candidates = 0;
+                if (log_on())
+                    std::fprintf(stderr, "stencil: tune %lldx%lldx%lld R%d %s: from the cache %s: %s\n",
+                                 (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, ctx->R,
+                                 storage_name(ctx->st), o.cache_path, tile_text(norm).c_str());
                 return STENCIL_OK;
             }
         }
@@ -1102,6 +1140,13 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
     if (o.candidates)
         for (int c = 0; c < nC && c < o.table_cap; ++c) o.candidates[c] = cands[c];
     cache_store(o.cache_path, ctx, cands[best], min_time, actual);
+    if (log_on())
+        std::fprintf(stderr,
+                     "stencil: tune %lldx%lldx%lld R%d %s%s: %d candidates x %d replicates x %d steps, chose %s, "
+                     "MinTime %.4f ms, ActualTime %.4f ms, gap %+.2f%%, default tile %.4f ms, %.2f s\n",
+                     (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, ctx->R, storage_name(ctx->st),
+                     two ? " two-step" : "", nC, n_rep, n_iter, tile_text(cands[best]).c_str(), min_time, actual,
+                     100.0 * report->gap, dtime, report->seconds);
     return STENCIL_OK;
 }
 
@@ -1492,6 +1537,10 @@ stencil_status stencil_batch_tune(const stencil_shot *shots, int32_t n, const st
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     for (int i = 0; i < n; ++i) shots[i].ctx->tile = cands[best][i];
+    if (log_on())
+        std::fprintf(stderr, "stencil: batch tune, %d shots: %d candidates x %d replicates x %d steps, chose %s, "
+                     "MinTime %.4f ms, ActualTime %.4f ms\n", n, nC, n_rep, n_iter, tile_text(cand_key[best]).c_str(),
+                     min_time, actual);
     report->tile = cand_key[best];
     report->min_time_ms = min_time;
     report->actual_time_ms = actual;

@@ -418,3 +418,67 @@ def test_batch_rejects_buffers_shared_between_shots():
         assert e.value.status == p.EALIAS
     for c in ctxs:
         p.stencil_destroy(c)
+
+
+@pytest.mark.parametrize("policy", ["worst", "min", "avg", "ob"])
+def test_select_skips_failed_candidates(policy):
+    # A candidate whose launch failed is timed as +inf. As long as every
+    # replicate has one finite entry, no rule picks a failed candidate, and the
+    # library agrees with the oracle's rule.
+    rng = np.random.default_rng(19)
+    for _ in range(200):
+        nn, nk, nc = (int(rng.integers(1, 3)), int(rng.integers(1, 5)), int(rng.integers(2, 7)))
+        t = rng.random(size=(nn, nk, nc)) + 1.0
+        t[rng.random(size=t.shape) < 0.4] = np.inf
+        for i in range(nn):
+            for k in range(nk):
+                if not np.isfinite(t[i, k]).any():
+                    t[i, k, int(rng.integers(0, nc))] = 1.5
+        ids = [list(range(i * nc, (i + 1) * nc)) for i in range(nn)]
+        got = p.stencil_select(t.tolist(), policy)
+        assert got == oracle.select_block(t.tolist(), ids, policy)
+        assert np.isfinite(got[1])
+
+
+def test_tune_cache_entries_at_init(tmp_path, monkeypatch):
+    # stencil_init takes the last matching line of STENCIL_TUNE_CACHE; lines
+    # that do not parse, belong to another grid, radius or storage, or name a
+    # tile no compiled kernel runs are ignored or fall back to the default.
+    cache = tmp_path / "cache.txt"
+    monkeypatch.setenv("STENCIL_TUNE_CACHE", str(cache))
+    ctx = _init(nx=64, ny=48, nz=40)
+    default = p.stencil_get_tile(ctx).as_dict()
+    p.stencil_destroy(ctx)
+    cache.write_text("garbage line\n"
+                     "gfx950 R4 f32 64 48 41 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another grid
+                     "gfx950 R5 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another radius
+                     "gfx950 R4 f16 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another storage
+                     "gfx950 R4 f32 64 48 40 3 18 40 1 16 4 1 0 1.0 1.0\n")  # a two-step entry
+    ctx = _init(nx=64, ny=48, nz=40)
+    assert p.stencil_get_tile(ctx).as_dict() == default
+    p.stencil_destroy(ctx)
+    with open(cache, "a") as f:
+        f.write("gfx950 R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n")
+    ctx = _init(nx=64, ny=48, nz=40)
+    t = p.stencil_get_tile(ctx)
+    assert (t.kind, t.bx, t.by, t.ry, t.dz, t.vw, t.pf) == (p.TILE_ZMARCH, 32, 8, 1, 16, 4, 0)
+    p.stencil_destroy(ctx)
+    with open(cache, "a") as f:
+        f.write("gfx950 R4 f32 64 48 40 2 7 3 1 16 4 1 0 1.0 1.0\n")  # no such kernel: default
+    ctx = _init(nx=64, ny=48, nz=40)
+    assert p.stencil_get_tile(ctx).as_dict() == default
+    p.stencil_destroy(ctx)
+
+
+def test_log_lines_on_request(monkeypatch, capfd):
+    monkeypatch.delenv("STENCIL_LOG", raising=False)
+    p.stencil_destroy(_init(nx=64, ny=48, nz=40))
+    assert "stencil:" not in capfd.readouterr().err
+    monkeypatch.setenv("STENCIL_LOG", "1")
+    ctx = _init(nx=64, ny=48, nz=40, tile=p.make_tile(bx=32, by=8, ry=1, dz=16))
+    err = capfd.readouterr().err
+    assert "stencil: init 64x48x40 R4 f32" in err and "zmarch 32x8 ry1 dz16 vw4" in err and "(given)" in err
+    p.stencil_destroy(ctx)
+    monkeypatch.setenv("STENCIL_LOG", "0")
+    p.stencil_destroy(_init(nx=64, ny=48, nz=40))
+    assert "stencil:" not in capfd.readouterr().err
