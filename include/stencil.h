@@ -54,7 +54,9 @@ typedef enum {
     STENCIL_ENOMEM = -3,        /* host allocation failed */
     STENCIL_EDEVICE = -4,       /* a HIP call failed (message in stencil_last_error) */
     STENCIL_EUNSUPPORTED = -5,  /* storage type or tile the library has no compiled kernel for */
-    STENCIL_EALIAS = -6         /* fields that must be distinct overlap (e.g. u_cur and the output) */
+    STENCIL_EALIAS = -6,        /* fields that must be distinct overlap (e.g. u_cur and the output) */
+    STENCIL_EDIVERGED = -7      /* a wavefield is no longer finite or exceeds a caller's limit (not
+                                   returned by the library's calls: see stencil_max_abs) */
 } stencil_status;
 
 typedef struct stencil_ctx stencil_ctx;  /* opaque */
@@ -363,6 +365,17 @@ int32_t stencil_pgrid(int64_t S, int32_t P, int64_t *out, int32_t cap);
  * per write (the bandwidth reference). Enqueued on `stream`. */
 stencil_status stencil_stream_probe(const void *a, const void *b, const void *c, void *out, int64_t nbytes,
                                     void *stream);
+
+/* Divergence watchdog: the largest magnitude of the wavefield u (the
+ * context's grid and storage type) into *out, a device float, in storage
+ * units (storage_scale * |u| for 16-bit storage): NaN if any value is NaN,
+ * +inf if any is infinite, else max |u|. Two launches on `stream` (a
+ * one-thread clear of *out, then a grid-stride reduction with an atomic
+ * maximum over the magnitude's bit pattern, which orders NaN above +inf above
+ * every finite value); no allocation and no host wait, so it can be
+ * captured. A caller checks *out every few steps and stops with
+ * STENCIL_EDIVERGED when it is not finite or exceeds its limit. */
+stencil_status stencil_max_abs(stencil_ctx *ctx, const void *u, float *out, void *stream);
 
 /* Streaming reference in the one-step sweep's access order, without the
  * stencil: out = (a + b) + c over [nz][ny][nx] FP32 fields (nx % 4 == 0,

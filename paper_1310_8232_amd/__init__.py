@@ -32,7 +32,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- status codes and enums (include/stencil.h) ----------------------------
-OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EUNSUPPORTED, EALIAS = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSTABLE, ENOMEM, EDEVICE, EUNSUPPORTED, EALIAS, EDIVERGED = 0, -1, -2, -3, -4, -5, -6, -7
 F32, F16, BF16 = 0, 1, 2
 STORAGES = {"f32": F32, "f16": F16, "bf16": BF16}
 TILE_AUTO, TILE_PLAIN, TILE_ZMARCH, TILE_ZMARCH2 = 0, 1, 2, 3
@@ -121,6 +121,7 @@ _sig = {
     "stencil_pgrid": (_i32, [_i64, _i32, ctypes.POINTER(_i64), _i32]),
     "stencil_stream_probe": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp]),
     "stencil_stream_probe_march": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp]),
+    "stencil_max_abs": (_i32, [_vp, _vp, _vp, _vp]),
     "stencil_strerror": (ctypes.c_char_p, [_i32]),
     "stencil_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -412,6 +413,14 @@ def stencil_stream_probe(a, b, c, out, nbytes: int, stream=None):
     _check(_lib.stencil_stream_probe(_ptr(a), _ptr(b), _ptr(c), _ptr(out), int(nbytes), _stream(stream)))
 
 
+def stencil_max_abs(ctx, u, out, stream=None):
+    """out (a float32 device tensor of at least one element) <- max |u| in
+    storage units: NaN if any value is NaN, +inf if any is infinite."""
+    if out.dtype.itemsize != 4 or out.numel() < 1:
+        raise ValueError("out must hold at least one 4-byte value")
+    _check(_lib.stencil_max_abs(ctx, _ptr(u), _ptr(out), _stream(stream)), ctx)
+
+
 def stencil_stream_probe_march(a, b, c, out, shape, stream=None):
     """out = (a + b) + c over [nz, ny, nx] FP32 fields in the sweep's access order."""
     nz, ny, nx = shape
@@ -491,15 +500,43 @@ class Propagator:
     def tile(self, t: StencilTile):
         stencil_set_tile(self.ctx, t)
 
+    def max_abs(self, u, out=None, stream=None):
+        """max |u| as a float32 device scalar (NaN if any value is NaN, +inf if
+        any is infinite), in the wavefield's own units; asynchronous."""
+        import torch
+        self._check_field(u)
+        if out is None:
+            out = torch.empty((), dtype=torch.float32, device=self.device)
+        stencil_max_abs(self.ctx, u, out, stream)
+        if self.storage_scale != 1.0:
+            out.div_(self.storage_scale)  # a power of two: exact
+        return out
+
+    def check_finite(self, u, limit: float = 0.0, stream=None) -> float:
+        """Waits for the stream and raises StencilError(EDIVERGED) when u holds
+        a NaN or an infinity, or (limit > 0) a magnitude above limit;
+        returns max |u|."""
+        import torch
+        m = float(self.max_abs(u, stream=stream).item())
+        if not (m == m) or m == float("inf") or (limit > 0 and m > limit):
+            raise StencilError(EDIVERGED, f"{stencil_strerror(EDIVERGED)}: max |u| = {m}")
+        return m
+
     def step(self, u_cur, u_prev_next, it: int = 0, src: StencilSrc | None = None, stream=None):
         self._check_field(u_cur)
         self._check_field(u_prev_next)
         stencil_step(self.ctx, self.kappa, u_cur, u_prev_next, it, src, stream)
 
     def run(self, u_cur, u_prev, nt: int, src: StencilSrc | None = None, it0: int = 0, stream=None,
-            temporal: int = 1, spare=None):
+            temporal: int = 1, spare=None, check_every: int = 0, limit: float = 0.0):
         """Advance nt steps from (u^{it0}, u^{it0-1}); returns the tensors now
         holding (u^{it0+nt}, u^{it0+nt-1}).
+
+        check_every = k > 0 is a divergence watchdog: after every k steps (and
+        at the end) the newest wavefield's max |u| is read back, and a NaN, an
+        infinity or (limit > 0) a value above limit raises
+        StencilError(EDIVERGED). Each check waits for the stream, so leave it
+        0 inside graph capture.
 
         temporal=2 uses two-step launches (bit-identical results), which need
         two more wavefield buffers: ``spare`` = (c, d), allocated if None; an
@@ -508,6 +545,18 @@ class Propagator:
         get back, in place, the two buffers that are free afterwards."""
         self._check_field(u_cur)
         self._check_field(u_prev)
+        if check_every < 0:
+            raise ValueError("check_every must be >= 0")
+        if check_every:
+            # The watchdog runs the loop in segments of check_every steps.
+            done = 0
+            a, b = u_cur, u_prev
+            while done < nt:
+                k = min(check_every, nt - done)
+                a, b = self.run(a, b, k, src, it0 + done, stream, temporal, spare)
+                self.check_finite(a, limit, stream)
+                done += k
+            return a, b
         a, b = u_cur, u_prev
         it = it0
         if temporal == 2 and nt >= 2:

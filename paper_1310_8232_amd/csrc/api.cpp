@@ -707,6 +707,7 @@ const char *stencil_strerror(stencil_status s)
     case STENCIL_EDEVICE: return "HIP device error";
     case STENCIL_EUNSUPPORTED: return "unsupported storage type or tile";
     case STENCIL_EALIAS: return "u_cur and u_prev_next overlap";
+    case STENCIL_EDIVERGED: return "the wavefield diverged (not finite or above the limit)";
     }
     return "unknown status";
 }
@@ -1580,6 +1581,18 @@ stencil_status stencil_stream_probe(const void *a, const void *b, const void *c,
         return STENCIL_EINVAL;
     hipError_t e = p1310::launch_stream(a, b, c, out, nbytes, (hipStream_t)stream);
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
+}
+
+stencil_status stencil_max_abs(stencil_ctx *ctx, const void *u, float *out, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (!u || !out) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    if (overlaps2(out, 4, u, npoints(ctx) * ctx->es)) return fail(ctx, STENCIL_EALIAS, "out lies inside the field");
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    hipError_t e = p1310::launch_max_abs(ctx->st, u, npoints(ctx), (unsigned int *)out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "max_abs launch");
+    return STENCIL_OK;
 }
 
 stencil_status stencil_stream_probe_march(const void *a, const void *b, const void *c, void *out, int64_t nx,

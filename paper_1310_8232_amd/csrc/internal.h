@@ -76,6 +76,8 @@ hipError_t launch_grad2(double *g, const float *mua, const float *mub, const flo
                         const float *u1, const float *u0, int64_t n, double scale, hipStream_t s);
 hipError_t launch_misfit(const float *tr, const float *obs, int64_t count, float *resid, double *misfit,
                          hipStream_t s);
+// Largest |u| (bit pattern, NaN above +inf above finite) of n stored values into *out.
+hipError_t launch_max_abs(int st, const void *u, int64_t n, unsigned int *out, hipStream_t s);
 hipError_t launch_stream_march(const void *a, const void *b, const void *c, void *out, int64_t nx, int64_t ny,
                               int64_t nz, hipStream_t s);
 hipError_t launch_stream(const void *a, const void *b, const void *c, void *out, int64_t nbytes, hipStream_t s);

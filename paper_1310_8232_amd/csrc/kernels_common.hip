@@ -297,6 +297,53 @@ __global__ void __launch_bounds__(kMisfitThreads) misfit_kernel(const float *tr,
     if (threadIdx.x == 0) *misfit = 0.5 * part[0];
 }
 
+
+// Divergence watchdog: the largest magnitude over n stored values as the
+// bit pattern of a non-negative float. For non-negative floats the unsigned
+// order of the patterns is the numeric order, NaN patterns lie above +inf,
+// so an unsigned maximum gives NaN if any value is NaN, else +inf if any is
+// infinite, else max |u|. Each workgroup reduces in LDS and adds one atomic.
+__global__ void __launch_bounds__(64) max_abs_clear_kernel(unsigned int *out)
+{
+    if (threadIdx.x == 0) *out = 0u;
+}
+
+template <typename ST>
+__global__ void __launch_bounds__(256) max_abs_kernel(const ST *u, int64_t n, unsigned int *out)
+{
+    __shared__ unsigned int part[256];
+    unsigned int m = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        m = max(m, __float_as_uint(fabsf((float)u[i])));
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = max(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, part[0]);
+}
+
+__global__ void __launch_bounds__(256) max_abs_kernel_vec4(const float4 *u, int64_t n4, unsigned int *out)
+{
+    __shared__ unsigned int part[256];
+    unsigned int m = 0u;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 v = u[i];
+        m = max(m, max(max(__float_as_uint(fabsf(v.x)), __float_as_uint(fabsf(v.y))),
+                       max(__float_as_uint(fabsf(v.z)), __float_as_uint(fabsf(v.w)))));
+    }
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = max(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, part[0]);
+}
+
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Streaming reference: out = a (+ b) (+ c), NIN inputs, one output. Each
@@ -527,6 +574,32 @@ hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, doub
     if (blocks > 16384) blocks = 16384;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(kappa_kernel, dim3((unsigned)blocks), dim3(256), 0, s, v, kappa, n, dt, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_abs(int st, const void *u, int64_t n, unsigned int *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(max_abs_clear_kernel, dim3(1), dim3(64), 0, s, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 1023) / 1024, 1), 4096);
+    switch (st) {
+    case kF32:
+        if (n % 4 == 0 && !((uintptr_t)u & 15u))
+            hipLaunchKernelGGL(max_abs_kernel_vec4, dim3((unsigned)blocks), dim3(256), 0, s, (const float4 *)u, n / 4,
+                               out);
+        else
+            hipLaunchKernelGGL(max_abs_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float *)u, n, out);
+        break;
+    case kF16:
+        hipLaunchKernelGGL(max_abs_kernel<_Float16>, dim3((unsigned)blocks), dim3(256), 0, s, (const _Float16 *)u, n,
+                           out);
+        break;
+    case kBF16:
+        hipLaunchKernelGGL(max_abs_kernel<__bf16>, dim3((unsigned)blocks), dim3(256), 0, s, (const __bf16 *)u, n, out);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -482,3 +482,17 @@ def test_log_lines_on_request(monkeypatch, capfd):
     monkeypatch.setenv("STENCIL_LOG", "0")
     p.stencil_destroy(_init(nx=64, ny=48, nz=40))
     assert "stencil:" not in capfd.readouterr().err
+
+
+def test_max_abs_validation():
+    ctx = _init(nx=16, ny=16, nz=16)
+    base = 1 << 40
+    n = 16 ** 3 * 4
+    with pytest.raises(p.StencilError) as e:
+        p._check(p._lib.stencil_max_abs(ctx, None, base, 0), ctx)
+    assert e.value.status == p.EINVAL
+    with pytest.raises(p.StencilError) as e:
+        p._check(p._lib.stencil_max_abs(ctx, base, base + n // 2, 0), ctx)
+    assert e.value.status == p.EALIAS
+    assert "diverged" in p.stencil_strerror(p.EDIVERGED)
+    p.stencil_destroy(ctx)
