@@ -32,8 +32,9 @@
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  * stream). The stepping calls (stencil_kappa, stencil_step, stencil_step_to,
- * stencil_step2, stencil_adjoint_step, stencil_gradient2, stencil_sample,
- * stencil_misfit, stencil_convert, stencil_batch_step) only enqueue work: no
+ * stencil_step2, stencil_adjoint_step, stencil_gradient2, stencil_gradient_terms,
+ * stencil_sample, stencil_misfit, stencil_convert, stencil_batch_step,
+ * stencil_max_abs) only enqueue work: no
  * allocation, no synchronisation, no host read of device memory, so they may
  * be captured in a HIP graph. stencil_tune and stencil_batch_tune synchronise
  * the stream.
@@ -241,6 +242,18 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
  * only (EUNSUPPORTED). Capture-safe. */
 stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void *mu_km1, const void *u_k,
                                  const void *u_km1, const void *u_km2, const void *u_km3, double *grad, void *stream);
+
+/* m = 1..4 consecutive gradient terms in one pass, for adjoint steps k,
+ * k-1, ..., k-m+1: grad += s mu[j] ((u[j] - 2 u[j+1]) + u[j+2]) for
+ * j = 0, 1, ..., m-1 in that order, s = -h^2/dt^2, each term formed in FP64
+ * and added as stencil_adjoint_step adds it, so the result has the bits of m
+ * single-term accumulations (stencil_gradient2 is m = 2). mu is a host array
+ * of m device pointers (mu^k, mu^{k-1}, ...), u a host array of m + 2
+ * (u^k, u^{k-1}, ..., u^{k-m-1}); FP32 fields of the grid, FP64 grad, which
+ * must not overlap another field (EALIAS). FP32 storage; capture-safe. Per
+ * point (2m + 2) x 4 B read and 16 B of grad read and written. */
+stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *const *mu, const void *const *u,
+                                      double *grad, void *stream);
 
 /* resid[i] = traces[i] - observed[i] (FP32, i < count; resid may be NULL) and
  * *misfit = 1/2 sum resid^2 accumulated in FP64 in a fixed order (device

@@ -101,6 +101,7 @@ _sig = {
     "stencil_adjoint_step": (_i32, [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(StencilSrc), _vp, _vp, _vp, _vp,
                                     _vp]),
     "stencil_gradient2": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "stencil_gradient_terms": (_i32, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp]),
     "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "stencil_batch_create": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
     "stencil_batch_step": (_i32, [_vp, _i64, _vp]),
@@ -266,6 +267,17 @@ def stencil_gradient2(ctx, mu_k, mu_km1, u_k, u_km1, u_km2, u_km3, grad, stream=
     """The gradient terms of adjoint steps k and k-1 in one pass (see the header)."""
     _check(_lib.stencil_gradient2(ctx, _ptr(mu_k), _ptr(mu_km1), _ptr(u_k), _ptr(u_km1), _ptr(u_km2), _ptr(u_km3),
                                   _ptr(grad), _stream(stream)), ctx)
+
+
+def stencil_gradient_terms(ctx, mu, u, grad, stream=None):
+    """m = len(mu) (1..4) consecutive gradient terms in one pass; u holds
+    m + 2 levels (u^k, u^{k-1}, ...). See the header."""
+    m = len(mu)
+    if len(u) != m + 2:
+        raise ValueError("u must hold len(mu) + 2 fields")
+    mus = (_vp * max(m, 1))(*[_ptr(x) for x in mu])
+    us = (_vp * (m + 2))(*[_ptr(x) for x in u])
+    _check(_lib.stencil_gradient_terms(ctx, int(m), mus, us, _ptr(grad), _stream(stream)), ctx)
 
 
 def stencil_misfit(traces, observed, resid, misfit, stream=None):

@@ -25,8 +25,8 @@ from dataclasses import dataclass
 
 import torch
 
-from . import (Propagator, StencilSrc, make_src, stencil_adjoint_step, stencil_gradient2, stencil_misfit,
-               stencil_sample, stencil_step, stencil_step_to, stencil_stream_probe)
+from . import (Propagator, StencilSrc, make_src, stencil_gradient_terms, stencil_misfit, stencil_sample,
+               stencil_step, stencil_step_to, stencil_stream_probe)
 
 
 @dataclass
@@ -99,28 +99,30 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
     src = survey.src()
     rsrc = make_src(survey.rec_idx, resid)
     grad = torch.zeros(prop.shape, dtype=torch.float64, device=prop.device)
-    mu_cur = torch.zeros(prop.shape, device=prop.device)   # mu^{k+1}
-    mu_prev = torch.zeros(prop.shape, device=prop.device)  # mu^{k+2}
-    state = [mu_cur, mu_prev]
+    # Four buffers of mu: the pair (mu^{k+1}, mu^{k+2}) that the next adjoint
+    # step reads, and room for up to four new levels whose gradient terms are
+    # then added in one pass.
+    bufs = [torch.zeros(prop.shape, device=prop.device) for _ in range(4)]
+    state = [bufs[0], bufs[1]]  # [mu^{k+1}, mu^{k+2}]
 
     def adjoint_range(k_hi, k_lo, level):
-        # Adjoint steps k = k_hi .. k_lo + 1 with level(j) = u^j. Steps go in
-        # pairs whose two gradient terms share one pass over memory
-        # (stencil_gradient2: the bits of two accumulating steps); an odd
-        # last step accumulates on its own.
+        # Adjoint steps k = k_hi .. k_lo + 1 with level(j) = u^j, in groups of
+        # up to four: each step writes mu^{k-j} out of place (the step with the
+        # residuals of row k-j-1 injected), then stencil_gradient_terms adds the
+        # group's terms in step order (the bits of one accumulation per step).
         k = k_hi
         while k > k_lo:
-            mc, mp = state
-            if k - 1 > k_lo:
-                stencil_adjoint_step(prop.ctx, prop.kappa, mc, mp, k - 1, rsrc)           # mu^k into mp
-                stencil_adjoint_step(prop.ctx, prop.kappa, mp, mc, k - 2, rsrc)           # mu^{k-1} into mc
-                stencil_gradient2(prop.ctx, mp, mc, level(k), level(k - 1), level(k - 2), level(k - 3), grad)
-                k -= 2
-            else:
-                stencil_adjoint_step(prop.ctx, prop.kappa, mc, mp, k - 1, rsrc, level(k), level(k - 1),
-                                     level(k - 2), grad)
-                state.reverse()
-                k -= 1
+            m = min(4, k - k_lo)
+            cur, prev = state
+            free = [x for x in bufs if x is not cur and x is not prev]
+            outs = (free + [prev, cur])[:m]  # prev is read last by step 0, cur by step 1
+            c, pv = cur, prev
+            for j in range(m):
+                stencil_step_to(prop.ctx, prop.kappa, c, pv, outs[j], k - j - 1, rsrc)  # mu^{k-j}
+                c, pv = outs[j], c
+            stencil_gradient_terms(prop.ctx, outs, [level(k - i) for i in range(m + 2)], grad)
+            state[0], state[1] = c, pv
+            k -= m
 
     if "levels" in ckpts:  # every level kept: no recompute
         L = ckpts["levels"]  # L[n + 1] = u^n

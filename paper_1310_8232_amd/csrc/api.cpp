@@ -1222,9 +1222,36 @@ stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void 
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
-    hipError_t e = p1310::launch_grad2(grad, (const float *)mu_k, (const float *)mu_km1, (const float *)u_k,
-                                       (const float *)u_km1, (const float *)u_km2, (const float *)u_km3, npoints(ctx),
-                                       scale, (hipStream_t)stream);
+    const float *mu[] = {(const float *)mu_k, (const float *)mu_km1};
+    const float *u[] = {(const float *)u_k, (const float *)u_km1, (const float *)u_km2, (const float *)u_km3};
+    hipError_t e = p1310::launch_gradn(2, grad, mu, u, npoints(ctx), scale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
+    return STENCIL_OK;
+}
+
+stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *const *mu, const void *const *u,
+                                      double *grad, void *stream)
+{
+    if (!ctx) return STENCIL_EINVAL;
+    if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "the gradient needs FP32 storage");
+    if (m < 1 || m > 4) return fail(ctx, STENCIL_EINVAL, "m must be 1..4");
+    if (!mu || !u || !grad) return fail(ctx, STENCIL_EINVAL, "null pointer");
+    const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+    const float *fm[4], *fu[6];
+    for (int j = 0; j < m; ++j) {
+        if (!mu[j]) return fail(ctx, STENCIL_EINVAL, "null pointer");
+        if (overlaps2(grad, gb, mu[j], fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
+        fm[j] = (const float *)mu[j];
+    }
+    for (int j = 0; j < m + 2; ++j) {
+        if (!u[j]) return fail(ctx, STENCIL_EINVAL, "null pointer");
+        if (overlaps2(grad, gb, u[j], fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
+        fu[j] = (const float *)u[j];
+    }
+    DeviceGuard g(ctx->d.device);
+    if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
+    const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
+    hipError_t e = p1310::launch_gradn(m, grad, fm, fu, npoints(ctx), scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
     return STENCIL_OK;
 }

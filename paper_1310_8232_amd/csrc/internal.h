@@ -72,8 +72,9 @@ hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, do
 hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s);
 hipError_t launch_grad(double *g, const float *mu, const float *un, const float *uc, const float *up, int64_t n,
                        double scale, hipStream_t s);
-hipError_t launch_grad2(double *g, const float *mua, const float *mub, const float *u3, const float *u2,
-                        const float *u1, const float *u0, int64_t n, double scale, hipStream_t s);
+// m = 1..4 consecutive gradient terms: mu[0..m-1], u[0..m+1] (see gradn_kernel).
+hipError_t launch_gradn(int m, double *g, const float *const *mu, const float *const *u, int64_t n, double scale,
+                        hipStream_t s);
 hipError_t launch_misfit(const float *tr, const float *obs, int64_t count, float *resid, double *misfit,
                          hipStream_t s);
 // Largest |u| (bit pattern, NaN above +inf above finite) of n stored values into *out.

@@ -229,46 +229,53 @@ __global__ void __launch_bounds__(256) grad_kernel_vec4(double *g, const float *
     }
 }
 
-// Two consecutive gradient terms in one pass (the adjoint steps k and k-1):
-// g = (g + s mu_a (u3 - 2 u2 + u1)) + s mu_b (u2 - 2 u1 + u0), each term
-// rounded and added exactly as the single-term kernel does, so the result is
-// the bits of two single-term passes; 24 B of FP32 reads and 16 B of FP64
-// read-modify-write per point instead of 2 x 32 B.
-__global__ void __launch_bounds__(256) grad2_kernel(double *g, const float *mua, const float *mub, const float *u3,
-                                                    const float *u2, const float *u1, const float *u0, int64_t n,
-                                                    double s)
+// M consecutive gradient terms in one pass (adjoint steps k, k-1, ..., k-M+1):
+// g = (((g + t_0) + t_1) + ...) with t_j = s mu_j ((u_j - 2 u_{j+1}) + u_{j+2}),
+// each term rounded and added exactly as the single-term kernel does, so the
+// result is the bits of M single-term passes. Per point: (2M + 2) FP32 reads
+// and one FP64 read-modify-write (for M = 4: 56 B instead of 4 x 32 B).
+constexpr int kMaxTerms = 4;
+struct GradTerms {
+    const float *mu[kMaxTerms];
+    const float *u[kMaxTerms + 2];
+};
+
+template <int M>
+__global__ void __launch_bounds__(256) gradn_kernel(double *g, GradTerms f, int64_t n, double s)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double a = ((double)u3[i] - 2.0 * (double)u2[i]) + (double)u1[i];
-        const double b = ((double)u2[i] - 2.0 * (double)u1[i]) + (double)u0[i];
-        g[i] = (g[i] + s * ((double)mua[i] * a)) + s * ((double)mub[i] * b);
+        double u[M + 2];
+#pragma unroll
+        for (int j = 0; j < M + 2; ++j) u[j] = (double)f.u[j][i];
+        double r = g[i];
+#pragma unroll
+        for (int j = 0; j < M; ++j) r = r + s * ((double)f.mu[j][i] * ((u[j] - 2.0 * u[j + 1]) + u[j + 2]));
+        g[i] = r;
     }
 }
 
-__global__ void __launch_bounds__(256) grad2_kernel_vec4(double *g, const float *mua, const float *mub,
-                                                         const float *u3, const float *u2, const float *u1,
-                                                         const float *u0, int64_t n4, double s)
+template <int M>
+__global__ void __launch_bounds__(256) gradn_kernel_vec4(double *g, GradTerms f, int64_t n4, double s)
 {
     typedef float f4v __attribute__((ext_vector_type(4)));
     typedef double d2v __attribute__((ext_vector_type(2)));
     const int64_t beg = (int64_t)blockIdx.x * kGradChunk;
     const int64_t end = (beg + kGradChunk < n4) ? beg + kGradChunk : n4;
     for (int64_t i = beg + threadIdx.x; i < end; i += 256) {
-        const f4v ma = __builtin_nontemporal_load((const f4v *)mua + i);
-        const f4v mb = __builtin_nontemporal_load((const f4v *)mub + i);
-        const f4v v3 = __builtin_nontemporal_load((const f4v *)u3 + i);
-        const f4v v2 = __builtin_nontemporal_load((const f4v *)u2 + i);
-        const f4v v1 = __builtin_nontemporal_load((const f4v *)u1 + i);
-        const f4v v0 = __builtin_nontemporal_load((const f4v *)u0 + i);
+        f4v m[M], v[M + 2];
+#pragma unroll
+        for (int j = 0; j < M; ++j) m[j] = __builtin_nontemporal_load((const f4v *)f.mu[j] + i);
+#pragma unroll
+        for (int j = 0; j < M + 2; ++j) v[j] = __builtin_nontemporal_load((const f4v *)f.u[j] + i);
         d2v *gp = (d2v *)g + 2 * i;
         double r[4] = {gp[0].x, gp[0].y, gp[1].x, gp[1].y};
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const double a = ((double)v3[e] - 2.0 * (double)v2[e]) + (double)v1[e];
-            const double b = ((double)v2[e] - 2.0 * (double)v1[e]) + (double)v0[e];
-            r[e] = (r[e] + s * ((double)ma[e] * a)) + s * ((double)mb[e] * b);
-        }
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int j = 0; j < M; ++j)
+                r[e] = r[e] + s * ((double)m[j][e] *
+                                   (((double)v[j][e] - 2.0 * (double)v[j + 1][e]) + (double)v[j + 2][e]));
         gp[0] = d2v{r[0], r[1]};
         gp[1] = d2v{r[2], r[3]};
     }
@@ -543,22 +550,43 @@ hipError_t launch_grad(double *g, const float *mu, const float *un, const float 
     return hipGetLastError();
 }
 
-hipError_t launch_grad2(double *g, const float *mua, const float *mub, const float *u3, const float *u2,
-                        const float *u1, const float *u0, int64_t n, double scale, hipStream_t s)
+hipError_t launch_gradn(int m, double *g, const float *const *mu, const float *const *u, int64_t n, double scale,
+                        hipStream_t s)
 {
-    if (n % 4 == 0 && !(((uintptr_t)g | (uintptr_t)mua | (uintptr_t)mub | (uintptr_t)u3 | (uintptr_t)u2 |
-                         (uintptr_t)u1 | (uintptr_t)u0) & 15u)) {
+    if (m < 1 || m > kMaxTerms) return hipErrorInvalidValue;
+    GradTerms f = {};
+    uintptr_t bits = (uintptr_t)g;
+    for (int j = 0; j < m; ++j) {
+        f.mu[j] = mu[j];
+        bits |= (uintptr_t)mu[j];
+    }
+    for (int j = 0; j < m + 2; ++j) {
+        f.u[j] = u[j];
+        bits |= (uintptr_t)u[j];
+    }
+    if (n % 4 == 0 && !(bits & 15u)) {
         const int64_t n4 = n / 4;
         const int64_t blocks = (n4 + kGradChunk - 1) / kGradChunk;
         if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(grad2_kernel_vec4, dim3((unsigned)blocks), dim3(256), 0, s, g, mua, mub, u3, u2, u1, u0,
-                           n4, scale);
+        const dim3 grid((unsigned)blocks), block(256);
+        switch (m) {
+        case 1: hipLaunchKernelGGL(gradn_kernel_vec4<1>, grid, block, 0, s, g, f, n4, scale); break;
+        case 2: hipLaunchKernelGGL(gradn_kernel_vec4<2>, grid, block, 0, s, g, f, n4, scale); break;
+        case 3: hipLaunchKernelGGL(gradn_kernel_vec4<3>, grid, block, 0, s, g, f, n4, scale); break;
+        default: hipLaunchKernelGGL(gradn_kernel_vec4<4>, grid, block, 0, s, g, f, n4, scale); break;
+        }
         return hipGetLastError();
     }
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(grad2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, mua, mub, u3, u2, u1, u0, n, scale);
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (m) {
+    case 1: hipLaunchKernelGGL(gradn_kernel<1>, grid, block, 0, s, g, f, n, scale); break;
+    case 2: hipLaunchKernelGGL(gradn_kernel<2>, grid, block, 0, s, g, f, n, scale); break;
+    case 3: hipLaunchKernelGGL(gradn_kernel<3>, grid, block, 0, s, g, f, n, scale); break;
+    default: hipLaunchKernelGGL(gradn_kernel<4>, grid, block, 0, s, g, f, n, scale); break;
+    }
     return hipGetLastError();
 }
 

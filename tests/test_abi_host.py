@@ -496,3 +496,23 @@ def test_max_abs_validation():
     assert e.value.status == p.EALIAS
     assert "diverged" in p.stencil_strerror(p.EDIVERGED)
     p.stencil_destroy(ctx)
+
+
+def test_gradient_terms_validation():
+    ctx = _init(nx=16, ny=16, nz=16)
+    base = 1 << 40
+    n = 16 ** 3 * 4
+    f = [base + i * 2 * n for i in range(10)]
+    g = base + 64 * n
+    for m in (0, 5):
+        mu = (p._vp * max(m, 1))(*f[:max(m, 1)])
+        u = (p._vp * (m + 2))(*f[4:4 + m + 2])
+        with pytest.raises(p.StencilError) as e:
+            p._check(p._lib.stencil_gradient_terms(ctx, m, mu, u, g, 0), ctx)
+        assert e.value.status == p.EINVAL
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_gradient_terms(ctx, f[:2], f[4:8], f[5] + 8, stream=0)  # grad inside a field
+    assert e.value.status == p.EALIAS
+    with pytest.raises(ValueError):
+        p.stencil_gradient_terms(ctx, f[:2], f[4:7], g, stream=0)
+    p.stencil_destroy(ctx)

@@ -78,6 +78,33 @@ def test_checkpoint_interval_does_not_change_bits():
         assert J == out[0][0] and np.array_equal(g, out[0][1]) and np.array_equal(tr, out[0][2])
 
 
+def test_gradient_terms_are_the_bits_of_single_terms():
+    # m terms in one pass (m = 1..4, also the scalar path on a grid whose point
+    # count is not a multiple of 4) equal m single-term passes; the one-term
+    # pass equals the accumulation inside stencil_adjoint_step.
+    for shape in ((40, 34, 30), (61, 29, 23)):
+        nx, ny, nz = shape
+        c, _ = _problem(nx, ny, nz, 8, seed=5)
+        prop = p.Propagator(cuda(c["m_cur"]), c["h"], c["dt"], 4, slowness2=True)
+        f = [cuda(workloads.random_field(nx, ny, nz, 90 + j)) for j in range(10)]
+        g0 = torch.from_numpy(np.random.default_rng(7).standard_normal((nz, ny, nx))).to("cuda:0")
+        log(f"case: gradient terms m = 1..4 against single terms, {shape}")
+        for m in (1, 2, 3, 4):
+            mu, u = f[:m], f[4:4 + m + 2]
+            ga, gb = g0.clone(), g0.clone()
+            p.stencil_gradient_terms(prop.ctx, mu, u, ga)
+            for j in range(m):
+                p.stencil_gradient_terms(prop.ctx, [mu[j]], u[j:j + 3], gb)
+            torch.cuda.synchronize()
+            assert torch.equal(ga, gb), f"m={m}"
+        lam_c, lam_p = f[0].clone(), f[1].clone()
+        ga, gb = g0.clone(), g0.clone()
+        p.stencil_adjoint_step(prop.ctx, prop.kappa, lam_c, lam_p, 3, None, f[4], f[5], f[6], ga)
+        p.stencil_gradient_terms(prop.ctx, [lam_p], [f[4], f[5], f[6]], gb)
+        torch.cuda.synchronize()
+        assert torch.equal(ga, gb)
+
+
 def test_autograd_function():
     c, obs = _problem(32, 28, 24, 40, seed=12)
     m = cuda(c["m_cur"]).requires_grad_(True)
