@@ -560,14 +560,20 @@ class Propagator:
         if check_every < 0:
             raise ValueError("check_every must be >= 0")
         if check_every:
-            # The watchdog runs the loop in segments of check_every steps.
+            # The watchdog runs the loop in segments of check_every steps; one
+            # spare list carries the two free buffers from segment to segment.
+            sp = list(spare) if spare is not None else None
+            if temporal == 2 and nt >= 2 and sp is None:
+                sp = [self.zeros(), self.zeros()]
             done = 0
             a, b = u_cur, u_prev
             while done < nt:
                 k = min(check_every, nt - done)
-                a, b = self.run(a, b, k, src, it0 + done, stream, temporal, spare)
+                a, b = self.run(a, b, k, src, it0 + done, stream, temporal, sp)
                 self.check_finite(a, limit, stream)
                 done += k
+            if isinstance(spare, list) and sp is not None:
+                spare[:] = sp
             return a, b
         a, b = u_cur, u_prev
         it = it0

@@ -93,6 +93,15 @@ def test_watchdog_run_same_bits_and_stops_on_divergence():
         a, b = prop.run(u0.clone(), um1.clone(), nt, src, temporal=temporal, check_every=5)
         torch.cuda.synchronize()
         assert torch.equal(a, ra) and torch.equal(b, rb)
+    # Two-step segments with the spares given as a tuple and as a list: the
+    # segments hand the free pair on, and a list comes back holding it.
+    for kind in (tuple, list):
+        spare = kind([prop.zeros(), prop.zeros()])
+        a, b = prop.run(u0.clone(), um1.clone(), nt, src, temporal=2, check_every=3, spare=spare)
+        torch.cuda.synchronize()
+        assert torch.equal(a, ra) and torch.equal(b, rb)
+        if kind is list:
+            assert len({t.data_ptr() for t in (a, b, *spare)}) == 4
     bad = u0.clone()
     bad.view(-1)[workloads.centre_index(nx, ny, nz)] = float("nan")
     with pytest.raises(p.StencilError) as e:
