@@ -289,7 +289,7 @@ def test_full_size_512_tuned_default_plain():
     v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=workloads.SEED)
     log(f"  inputs {time.time() - t0:.1f}s")
     prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
-    rep, _, _ = prop.tune(parts=3, n_iter=5, n_rep=2)
+    rep, _, _ = prop.tune(n_iter=10, n_rep=3)  # the bench's search: every compiled tile
     log(f"  tuned {rep['tile']} nC={rep['n_candidates']} {rep['seconds']:.1f}s")
     tuned = prop.tile
     del prop
@@ -316,7 +316,7 @@ def _throughput_workload_vs_oracle(nt):
     c = workloads.config_layered(512, 512, 512, nt=nt)
     log(f"case: 512^3 throughput workload from rest, searched tile, {nt} steps vs oracle")
     prop = p.Propagator(cuda(c["v"]), c["h"], c["dt"], 4, vmax=c["vmax"])
-    rep, _, _ = prop.tune(parts=3, n_iter=5, n_rep=2)
+    rep, _, _ = prop.tune(n_iter=10, n_rep=3)  # the bench's search: every compiled tile
     tile = prop.tile
     del prop
     torch.cuda.empty_cache()
