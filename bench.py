@@ -31,8 +31,11 @@ METRIC = "Gpoint-updates/s + % of HBM roofline, 512^3 8th-order FP32 vs plain ti
 
 
 def sweep_source_hash() -> str:
+    """Hash of the sources that define the sweep kernels (one- and two-step)
+    and their instantiations: counter summaries taken on other code do not
+    apply."""
     h = hashlib.sha256()
-    for f in ("sweep.hpp",):
+    for f in ("internal.h", "sweep.hpp", "sweep2.hpp", "kernels_radius.hip"):
         with open(os.path.join(ROOT, "paper_1310_8232_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -79,6 +82,18 @@ def time_steps(prop, a, b, nsteps, it0, src, stream, temporal=1, spare=None, nse
     return total, a, b, [ev[k].elapsed_time(ev[k + 1]) for k in range(nseg)]
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (Linux /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, budget_s: float):
     import numpy as np
 
@@ -104,7 +119,7 @@ def cpu_baseline(cfg, budget_s: float):
     t3 = time.perf_counter() - t0
     oracle.set_num_threads(cores)
     return {"value": npts * steps / (t1 + t2) / 1e9, "unit": "Gpt/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"FP64 oracle, {steps} leapfrog steps of the same {cfg['nx']}x{cfg['ny']}x{cfg['nz']} "
                       f"layered workload from rest (source on), {t1 + t2:.1f} s",
             "single_thread": {"value": npts / t3 / 1e9, "unit": "Gpt/s", "sample": f"1 step, {t3:.1f} s"}}
@@ -603,7 +618,7 @@ def main(argv=None):
     del a, b, spare
     s_ms, s_gbs = stream_rate(512, 3, 20, 3)
     m_ms, m_gbs = stream_march_rate(n, 20, 3) if n % 4 == 0 else (None, None)
-    sweep_gbs = npts * 16 / (step_ms * 1e-3) / 1e9
+    sweep_gbs = achieved  # algorithmic bytes of the launches that ran (16 B/update, or 20 B per two)
     ceiling = {"stream_3in_1out_gbs": round(s_gbs, 1),
                "stream_sweep_order_gbs": None if m_gbs is None else round(m_gbs, 1),
                "sweep_frac_of_stream": round(sweep_gbs / max(s_gbs, m_gbs or 0.0), 4)}
@@ -620,7 +635,7 @@ def main(argv=None):
                    "timed_segments": seg, "stream_ceiling": ceiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic if temporal == 1 else None},
+                     "traffic": traffic},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -131,7 +131,8 @@ typedef struct {
     int32_t warmup;          /* untimed steps before each timing; 0 = 2, -1 = none */
     int32_t parts;           /* 0 = every legal tile x the dz list; P >= 2 = Section 3.7's P-part grid */
     int32_t include_plain;   /* 1 = also time plain-tiling candidates */
-    const char *cache_path;  /* tune cache file (read before, written after); NULL = none */
+    const char *cache_path;  /* tune cache file (read before, written after); NULL = none. Only
+                                entries written by a library with the same stencil_build_id are read */
     double *table;           /* optional out: [n_rep][table_cap] times in ms (row-major) */
     stencil_tile *candidates;/* optional out: [table_cap] candidate tiles in timing order */
     int32_t table_cap;
@@ -154,11 +155,12 @@ typedef struct {
 
 /* Create a context. Validates sizes, radius, storage, h, dt, vmax (> 0) and
  * the stability limit vmax*dt/h <= stencil_cfl_limit(radius) (EUNSTABLE).
- * Host-only: no HIP call. *out is set only on success.
+ * Host-only: no device call. *out is set only on success.
  * Environment: STENCIL_TUNE_CACHE names a tune cache file whose last entry
- * for this grid, radius and storage gives the initial tile when d->tile is
- * kind 0 (unreadable lines and tiles no kernel runs are ignored: built-in
- * default); STENCIL_LOG (anything but empty or "0") prints one line to stderr
+ * for this grid, radius and storage, written by a library with the same
+ * stencil_build_id, gives the initial tile when d->tile is kind 0 (unreadable
+ * lines, entries of another build and tiles no kernel runs are ignored:
+ * built-in default); STENCIL_LOG (anything but empty or "0") prints one line to stderr
  * per context created and per search (stencil_tune, stencil_batch_tune). */
 stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out);
 
@@ -398,6 +400,12 @@ stencil_status stencil_max_abs(stencil_ctx *ctx, const void *u, float *out, void
  * sweep's own access pattern. Enqueued on `stream`. */
 stencil_status stencil_stream_probe_march(const void *a, const void *b, const void *c, void *out, int64_t nx,
                                           int64_t ny, int64_t nz, void *stream);
+
+/* Identity of this library's code as the tune cache records it (static
+ * storage): "<offload arch>/hip<compile-time HIP version>/rt<HIP runtime
+ * version>/src<hash of the kernel and runtime sources>". A tile measured
+ * with one build is not taken as the best tile of another. */
+const char *stencil_build_id(void);
 
 /* Message for a status code (static storage). */
 const char *stencil_strerror(stencil_status s);

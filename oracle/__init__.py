@@ -13,7 +13,8 @@ Contents
 * ``select_block``: the three-stage blocksize selection of Section 3.3
   (Eqs. 1-3 and the stage-3 rule), as a pure function of a timing table.
 * ``pgrid``: the per-dimension candidate lists of Section 3.7.
-* ``rel_l2``: the comparison measure used against the GPU path.
+* ``rel_l2``, ``max_rel``: the comparison measures used against the GPU path
+  (a global one and a per-element one).
 """
 from __future__ import annotations
 
@@ -150,6 +151,25 @@ def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
     """||a - ref||_2 / ||ref||_2, accumulated in FP64."""
     a = np.asarray(a, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()
+    if a.size != ref.size:
+        raise ValueError("a and ref must hold the same number of values")
     den = float(np.sqrt(np.dot(ref, ref)))
     num = float(np.sqrt(np.dot(a - ref, a - ref)))
     return num / den if den > 0 else num
+
+
+def max_rel(a: np.ndarray, ref: np.ndarray) -> float:
+    """max_i |a_i - ref_i| / max_i |ref_i| in FP64: the largest single-point
+    deviation, on the scale of the reference's largest value (a zero
+    reference gives the largest absolute deviation). A defect confined to a
+    few points, which a global norm over a large grid can hide, shows here."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    if a.size != ref.size:
+        raise ValueError("a and ref must hold the same number of values")
+    if a.size == 0:
+        return 0.0
+    den = float(np.max(np.abs(ref)))
+    num = float(np.max(np.abs(a - ref)))
+    return num / den if den > 0 else num
+

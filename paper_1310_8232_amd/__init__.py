@@ -124,6 +124,7 @@ _sig = {
     "stencil_stream_probe_march": (_i32, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp]),
     "stencil_max_abs": (_i32, [_vp, _vp, _vp, _vp]),
     "stencil_strerror": (ctypes.c_char_p, [_i32]),
+    "stencil_build_id": (ctypes.c_char_p, []),
     "stencil_last_error": (ctypes.c_char_p, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
@@ -188,6 +189,11 @@ def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile 
     out = _vp()
     _check(_lib.stencil_init(ctypes.byref(d), ctypes.byref(out)))
     return out.value
+
+
+def stencil_build_id() -> str:
+    """The code identity that tune cache entries carry."""
+    return _lib.stencil_build_id().decode()
 
 
 def stencil_destroy(ctx):

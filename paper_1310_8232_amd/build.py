@@ -2,10 +2,18 @@
 
 Objects go to paper_1310_8232_amd/_build/; the shared library is written next
 to this file, where the binding loads it. Compiles every time it is called.
+
+Every device compile asks hipcc for its per-kernel resource remarks
+(-Rpass-analysis=kernel-resource-usage). The build fails when any kernel
+spills SGPRs or VGPRs or uses per-lane scratch: spilled registers change a
+kernel's schedule and memory traffic in ways the tests do not see, so the
+product carries none. The per-kernel table is written to
+_build/resource_usage.txt.
 """
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 
@@ -18,7 +26,53 @@ RADII = (3, 4, 5)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-Wno-unused-command-line-argument"]
+          "-Wno-unused-command-line-argument", "-Rpass-analysis=kernel-resource-usage"]
+USAGE = os.path.join(OUT, "resource_usage.txt")
+
+_REMARK = re.compile(r"remark:\s+(Function Name|TotalSGPRs|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|"
+                     r"Occupancy \[waves/SIMD\]|SGPRs Spill|VGPRs Spill|LDS Size \[bytes/block\]):\s*(\S+)")
+
+
+def parse_resource_usage(text: str) -> list:
+    """Per-kernel records from hipcc's kernel-resource-usage remarks, in the
+    order printed: dicts with the kernel's (mangled) name and its counts."""
+    out, cur = [], None
+    for line in text.splitlines():
+        m = _REMARK.search(line)
+        if not m:
+            continue
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = {"name": val}
+            out.append(cur)
+        elif cur is not None:
+            k = key.split(" [")[0].replace(" ", "_").lower()
+            cur[k] = int(val) if val.lstrip("-").isdigit() else val
+    return out
+
+
+def spill_offenders(records: list) -> list:
+    """Kernels that spill registers or use scratch memory."""
+    return [r for r in records
+            if r.get("sgprs_spill", 0) or r.get("vgprs_spill", 0) or r.get("scratchsize", 0)]
+
+
+ARCH = "gfx950"
+
+
+def source_hash() -> str:
+    """Hash of every source compiled into the library and of its public
+    header: the code identity that tune cache entries carry."""
+    import hashlib
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".h", ".cpp")))
+    for n in names:
+        h.update(n.encode() + b"\0")
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(HERE, "..", "include", "stencil.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _jobs():
@@ -29,7 +83,8 @@ def _jobs():
     objs.append((os.path.join(OUT, "kernels_common.o"),
                  [HIPCC, *COMMON, "-c", os.path.join(CSRC, "kernels_common.hip")]))
     objs.append((os.path.join(OUT, "api.o"),
-                 [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, "api.cpp")]))
+                 [HIPCC, *COMMON, f'-DP1310_SOURCE_HASH="{source_hash()}"', f'-DP1310_ARCH="{ARCH}"',
+                  "-x", "hip", "-c", os.path.join(CSRC, "api.cpp")]))
     return objs
 
 
@@ -42,15 +97,33 @@ def build(verbose: bool = False) -> str:
             print(" ".join(full), file=sys.stderr)
         procs.append((obj, full, subprocess.Popen(full, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
+    records = []
     for obj, full, p in procs:
         out, _ = p.communicate()
-        text = "\n".join(l for l in out.decode(errors="replace").splitlines() if "packed-fp32-ops" not in l)
+        raw = out.decode(errors="replace")
+        records += parse_resource_usage(raw)
+        # Everything but the resource remarks (and their source excerpts) and
+        # the host pass's note about the packed-FP32 feature.
+        text = "\n".join(l for l in raw.splitlines()
+                         if "packed-fp32-ops" not in l and "kernel-resource-usage" not in l
+                         and not re.match(r"^\s*(\d+ \||\|)", l))
         if p.returncode != 0:
             failed.append((obj, text))
         elif verbose and text.strip():
             print(text, file=sys.stderr)
     if failed:
         raise RuntimeError("hipcc failed:\n" + "\n\n".join(f"{o}:\n{t}" for o, t in failed))
+    with open(USAGE, "w") as f:
+        for r in records:
+            f.write(" ".join(f"{k}={v}" for k, v in r.items()) + "\n")
+    if not records:
+        raise RuntimeError("hipcc printed no kernel resource remarks; the spill check cannot run")
+    bad = spill_offenders(records)
+    if bad:
+        raise RuntimeError("kernels spill registers or use scratch (see " + USAGE + "):\n" +
+                           "\n".join(f"  {r['name']}: SGPR spill {r.get('sgprs_spill')}, "
+                                      f"VGPR spill {r.get('vgprs_spill')}, scratch {r.get('scratchsize')} B/lane"
+                                      for r in bad))
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + [o for o, _ in _jobs()]
     if verbose:
         print(" ".join(link), file=sys.stderr)

@@ -299,6 +299,14 @@ int32_t max_dz(const stencil_ctx *ctx, int halo_planes)
     return dz < 1 ? 0 : (int32_t)std::min<int64_t>(dz, 1 << 30);
 }
 
+// The untuned tile. Shapes from full searches at 64^3 .. 1024x1024x512
+// (R = 3, 4, 5; FP32): 256 x 16 points (64 x 8 threads, two rows each) for
+// widths that are multiples of 256 from 512 up, 128 x 8 points from 128 up,
+// 64 x 8 below; the march depth is the deepest of 256, 128, ..., 4 planes
+// that still gives at least 512 workgroups (two per CU), so small grids fill
+// the device with shallow marches and large ones keep the z halo small.
+// Against the searched tile at those shapes: 1.00 at 512^3 (R = 4, 5), 10%
+// slower on average, 33% at most (unaligned widths of 200 and 300).
 stencil_tile default_tile(const stencil_ctx *ctx)
 {
     stencil_tile t = {};
@@ -310,12 +318,18 @@ stencil_tile default_tile(const stencil_ctx *ctx)
         return t;
     }
     t.kind = STENCIL_TILE_ZMARCH;
+    const int64_t nx = ctx->d.nx, ny = ctx->d.ny, nz = ctx->d.nz;
     const int vw = auto_vw(ctx);
     if (vw >= 4) {
-        t.bx = 16;
-        t.by = 8;
-        t.ry = 2;
         t.vw = 4;
+        t.by = 8;
+        if (nx >= 512 && nx % 256 == 0) {
+            t.bx = 64;
+            t.ry = 2;
+        } else {
+            t.bx = nx >= 128 ? 32 : 16;
+            t.ry = 1;
+        }
     } else if (vw == 2) {
         t.bx = 64;
         t.by = 4;
@@ -327,7 +341,15 @@ stencil_tile default_tile(const stencil_ctx *ctx)
         t.ry = ctx->st == p1310::kF32 ? 2 : 1;
         t.vw = 1;
     }
-    t.dz = std::min<int32_t>(64, max_dz(ctx, 2 * ctx->R));
+    const int64_t cols = ((nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw)) *
+                         ((ny + (int64_t)t.by * t.ry - 1) / ((int64_t)t.by * t.ry));
+    int32_t dz = 4;
+    for (int32_t d : {256, 128, 64, 32, 16, 8, 4})
+        if (cols * ((nz + d - 1) / d) >= 512) {
+            dz = d;
+            break;
+        }
+    t.dz = std::min<int32_t>(dz, max_dz(ctx, 2 * ctx->R));
     t.xcd = 1;
     t.pf = 0;
     return t;
@@ -338,8 +360,9 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
     stencil_tile t = {};
     t.kind = STENCIL_TILE_ZMARCH2;
     if (vec4_ok(ctx)) {
-        t.bx = 18;
-        t.by = 40;
+        // 18 x 40 is not compiled for R = 5 (it would spill registers).
+        t.bx = ctx->R <= 4 ? 18 : 16;
+        t.by = ctx->R <= 4 ? 40 : 32;
         t.vw = 4;
     } else {
         t.bx = 32;
@@ -354,9 +377,32 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
 
 // --------------------------------------------------------------------------
 // Tune cache: one line per entry,
-//   gfx950 R<r> f32 <nx> <ny> <nz> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms> <actual_ms>
-// The last matching line wins.
+//   v2 <build id> R<r> <storage> <nx> <ny> <nz> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms> <actual_ms>
+// where the build id (stencil_build_id) names the offload architecture, the
+// HIP version the kernels were compiled with, the HIP runtime in use and a
+// hash of the kernel and runtime sources. An entry measured with other code
+// (another build id, or the unversioned format of earlier builds) is
+// ignored: its tile may no longer be the fastest. The last matching line wins.
 // --------------------------------------------------------------------------
+#ifndef P1310_SOURCE_HASH
+#define P1310_SOURCE_HASH "unknown"
+#endif
+#ifndef P1310_ARCH
+#define P1310_ARCH "gfx950"
+#endif
+
+const std::string &build_id()
+{
+    static const std::string id = [] {
+        int rt = 0;
+        if (hipRuntimeGetVersion(&rt) != hipSuccess) rt = -1;
+        char b[160];
+        std::snprintf(b, sizeof b, "%s/hip%d/rt%d/src%s", P1310_ARCH, (int)HIP_VERSION, rt, P1310_SOURCE_HASH);
+        return std::string(b);
+    }();
+    return id;
+}
+
 bool cache_lookup(const char *path, const stencil_ctx *ctx, bool two, stencil_tile *t, double *mn, double *act)
 {
     if (!path || !*path) return false;
@@ -364,18 +410,19 @@ bool cache_lookup(const char *path, const stencil_ctx *ctx, bool two, stencil_ti
     if (!f) return false;
     char line[512];
     bool found = false;
+    char want[8];
+    std::snprintf(want, sizeof want, "R%d", ctx->R);
+    static const char *kst[] = {"f32", "f16", "bf16"};
     while (std::fgets(line, sizeof line, f)) {
-        char arch[32], rr[8], dt[8];
+        char ver[8], id[160], rr[8], dt[8];
         long long nx, ny, nz;
         stencil_tile c = {};
         double a = 0, b = 0;
-        int n = std::sscanf(line, "%31s %7s %7s %lld %lld %lld %d %d %d %d %d %d %d %d %lf %lf", arch, rr, dt, &nx, &ny,
-                            &nz, &c.kind, &c.bx, &c.by, &c.ry, &c.dz, &c.vw, &c.xcd, &c.pf, &a, &b);
-        if (n != 16) continue;
-        char want[8];
-        std::snprintf(want, sizeof want, "R%d", ctx->R);
-        static const char *kst[] = {"f32", "f16", "bf16"};
-        if (std::strcmp(arch, "gfx950") || std::strcmp(rr, want) || std::strcmp(dt, kst[ctx->st])) continue;
+        int n = std::sscanf(line, "%7s %159s %7s %7s %lld %lld %lld %d %d %d %d %d %d %d %d %lf %lf", ver, id, rr, dt,
+                            &nx, &ny, &nz, &c.kind, &c.bx, &c.by, &c.ry, &c.dz, &c.vw, &c.xcd, &c.pf, &a, &b);
+        if (n != 17) continue;
+        if (std::strcmp(ver, "v2") || build_id() != id) continue;
+        if (std::strcmp(rr, want) || std::strcmp(dt, kst[ctx->st])) continue;
         if (nx != ctx->d.nx || ny != ctx->d.ny || nz != ctx->d.nz) continue;
         if ((c.kind == STENCIL_TILE_ZMARCH2) != two) continue;
         *t = c;
@@ -393,9 +440,9 @@ void cache_store(const char *path, const stencil_ctx *ctx, const stencil_tile &t
     FILE *f = std::fopen(path, "a");
     if (!f) return;
     static const char *kst[] = {"f32", "f16", "bf16"};
-    std::fprintf(f, "gfx950 R%d %s %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", ctx->R, kst[ctx->st],
-                 (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, t.kind, t.bx, t.by, t.ry, t.dz,
-                 t.vw, t.xcd, t.pf, mn, act);
+    std::fprintf(f, "v2 %s R%d %s %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", build_id().c_str(), ctx->R,
+                 kst[ctx->st], (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, t.kind, t.bx, t.by,
+                 t.ry, t.dz, t.vw, t.xcd, t.pf, mn, act);
     std::fclose(f);
 }
 
@@ -713,6 +760,8 @@ const char *stencil_strerror(stencil_status s)
 }
 
 const char *stencil_last_error(const stencil_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+const char *stencil_build_id(void) { return build_id().c_str(); }
 
 double stencil_cfl_limit(int32_t radius) { return radius_ok(radius) ? cfl_limit_of(radius) : -1.0; }
 

@@ -32,15 +32,21 @@ namespace p1310 {
 // eight-point vector of 16-bit values is one 16-byte access), one-point rows,
 // and tiles of 16 and 32 rows (less y halo per point).
 #if RADIUS >= 4
+// Eight-point tiles of four rows, and the prefetching eight-point tile, spill
+// registers at R = 5 (4-6 VGPRs); they are compiled for R = 4 only.
+#if RADIUS == 4
+#define ZV16_R4ONLY(STT) ZVS(32, 4, 1, 8, 0, STT) ZVS(64, 4, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 1, STT)
+#else
+#define ZV16_R4ONLY(STT)
+#endif
 #define ZV16(STT)                                                                                \
     ZVS(16, 8, 1, 4, 0, STT) ZVS(16, 8, 2, 4, 0, STT) ZVS(32, 8, 1, 4, 0, STT)                  \
     ZVS(32, 4, 2, 4, 0, STT) ZVS(64, 4, 1, 4, 0, STT) ZVS(64, 4, 2, 4, 0, STT)                  \
     ZVS(16, 16, 1, 4, 0, STT) ZVS(64, 4, 1, 4, 1, STT) ZVS(64, 4, 1, 1, 0, STT)                  \
     ZVS(128, 2, 1, 4, 0, STT) ZVS(32, 16, 1, 4, 0, STT) ZVS(64, 8, 1, 4, 0, STT)                 \
-    ZVS(16, 8, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 0, STT) ZVS(32, 4, 1, 8, 0, STT)                   \
-    ZVS(64, 4, 1, 8, 0, STT) ZVS(16, 16, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 1, STT)                  \
+    ZVS(16, 8, 1, 8, 0, STT) ZVS(32, 8, 1, 8, 0, STT) ZVS(16, 16, 1, 8, 0, STT)                  \
     ZVS(32, 16, 2, 4, 0, STT) ZVS(16, 16, 2, 4, 0, STT) ZVS(32, 8, 2, 4, 0, STT)                 \
-    ZVS(64, 8, 2, 4, 0, STT)
+    ZVS(64, 8, 2, 4, 0, STT) ZV16_R4ONLY(STT)
 #else
 #define ZV16(STT)
 #endif
@@ -64,14 +70,24 @@ static const ZVariant kTable[] = {
     ZV16(kF16) ZV16(kBF16)
 };
 
-// Two-step kernels (RY = 1, FP32 storage): (BX, BY, VW, PF).
+// Two-step kernels (RY = 1, FP32 storage): (BX, BY, VW, PF). The 8 x 64
+// tile with prefetch is not compiled: a branch-free build of the two-step
+// kernel gave run-to-run differing values on it and no cause was shown.
 #define Z2V(BX, BY, VW, PF)                                                                       \
     {RADIUS, BX, BY, VW, PF, kF32, zmarch2_kernel<RADIUS, BX, BY, VW, PF, float>, BX * BY,       \
      BX * VW - 2 * ((VW == 1) ? RADIUS : ((RADIUS + VW - 1) / VW) * VW), BY - 2 * RADIUS},
 
+// The 18-thread-wide tiles (720 and 576 threads, at most 168 VGPRs per lane)
+// spill at R = 5 and are compiled for R = 3, 4 only.
+#if RADIUS <= 4
+#define Z2V_WIDE Z2V(18, 40, 4, 0) Z2V(18, 32, 4, 0)
+#else
+#define Z2V_WIDE
+#endif
+
 static const Z2Variant kTable2[] = {
-    Z2V(16, 32, 4, 0) Z2V(16, 32, 4, 1) Z2V(18, 40, 4, 0) Z2V(18, 32, 4, 0) Z2V(16, 24, 4, 0)
-    Z2V(8, 64, 4, 1) Z2V(32, 16, 1, 0)
+    Z2V(16, 32, 4, 0) Z2V(16, 32, 4, 1) Z2V_WIDE Z2V(16, 24, 4, 0)
+    Z2V(32, 16, 1, 0)
 };
 
 const Z2Variant *P1310_CAT(zmarch2_table_r, RADIUS)(int *n)

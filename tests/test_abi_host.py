@@ -440,6 +440,10 @@ def test_select_skips_failed_candidates(policy):
         assert np.isfinite(got[1])
 
 
+def _entry(rest, bid=None):
+    return f"v2 {bid or p.stencil_build_id()} {rest}\n"
+
+
 def test_tune_cache_entries_at_init(tmp_path, monkeypatch):
     # stencil_init takes the last matching line of STENCIL_TUNE_CACHE; lines
     # that do not parse, belong to another grid, radius or storage, or name a
@@ -449,24 +453,79 @@ def test_tune_cache_entries_at_init(tmp_path, monkeypatch):
     ctx = _init(nx=64, ny=48, nz=40)
     default = p.stencil_get_tile(ctx).as_dict()
     p.stencil_destroy(ctx)
-    cache.write_text("garbage line\n"
-                     "gfx950 R4 f32 64 48 41 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another grid
-                     "gfx950 R5 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another radius
-                     "gfx950 R4 f16 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n"    # another storage
-                     "gfx950 R4 f32 64 48 40 3 18 40 1 16 4 1 0 1.0 1.0\n")  # a two-step entry
+    cache.write_text("garbage line\n" +
+                     _entry("R4 f32 64 48 41 2 32 8 1 16 4 1 0 1.0 1.0") +    # another grid
+                     _entry("R5 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0") +    # another radius
+                     _entry("R4 f16 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0") +    # another storage
+                     _entry("R4 f32 64 48 40 3 18 40 1 16 4 1 0 1.0 1.0"))    # a two-step entry
     ctx = _init(nx=64, ny=48, nz=40)
     assert p.stencil_get_tile(ctx).as_dict() == default
     p.stencil_destroy(ctx)
     with open(cache, "a") as f:
-        f.write("gfx950 R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0\n")
+        f.write(_entry("R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0"))
     ctx = _init(nx=64, ny=48, nz=40)
     t = p.stencil_get_tile(ctx)
     assert (t.kind, t.bx, t.by, t.ry, t.dz, t.vw, t.pf) == (p.TILE_ZMARCH, 32, 8, 1, 16, 4, 0)
     p.stencil_destroy(ctx)
     with open(cache, "a") as f:
-        f.write("gfx950 R4 f32 64 48 40 2 7 3 1 16 4 1 0 1.0 1.0\n")  # no such kernel: default
+        f.write(_entry("R4 f32 64 48 40 2 7 3 1 16 4 1 0 1.0 1.0"))  # no such kernel: default
     ctx = _init(nx=64, ny=48, nz=40)
     assert p.stencil_get_tile(ctx).as_dict() == default
+    p.stencil_destroy(ctx)
+
+
+def test_build_id_names_arch_versions_and_source_hash():
+    bid = p.stencil_build_id()
+    arch, hip, rt, src = bid.split("/")
+    assert arch == "gfx950" and hip.startswith("hip") and rt.startswith("rt")
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_p1310_build", os.path.join(ROOT, "paper_1310_8232_amd", "build.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    # The library was built from the sources in the tree.
+    assert src == "src" + b.source_hash()
+
+
+def _tune_from_cache_only(ctx, cache):
+    # Fake, non-overlapping, aligned field addresses: the call either returns
+    # a cache entry (no device work) or goes on to the device, which the
+    # context's device number 1000 does not name (EDEVICE before any launch).
+    n = 64 * 48 * 40 * 4
+    base = 1 << 40
+    rep = p.StencilTuneReport()
+    opts = p.StencilTuneOpts()
+    opts.cache_path = str(cache).encode()
+    st = p._lib.stencil_tune(ctx, base, base + n, base + 2 * n, ctypes.byref(opts), ctypes.byref(rep), None)
+    return st, rep
+
+
+def test_tune_cache_ignores_entries_of_other_builds(tmp_path, monkeypatch):
+    # An entry measured with other code (another source hash, compiler or
+    # runtime version, or the unversioned format) is stale: neither init nor
+    # stencil_tune takes it.
+    cache = tmp_path / "cache.txt"
+    bid = p.stencil_build_id()
+    arch, hip, rt, src = bid.split("/")
+    stale = [f"{arch}/{hip}/{rt}/src0123456789abcdef", f"{arch}/hip1/{rt}/{src}", f"{arch}/{hip}/rt1/{src}",
+             f"gfx942/{hip}/{rt}/{src}"]
+    good = "R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0"
+    cache.write_text("".join(_entry(good, b) for b in stale) + "gfx950 " + good + "\n")
+    monkeypatch.setenv("STENCIL_TUNE_CACHE", str(cache))
+    monkeypatch.delenv("STENCIL_LOG", raising=False)
+    ctx = _init(nx=64, ny=48, nz=40, device=1000)
+    t = p.stencil_get_tile(ctx)
+    assert (t.bx, t.by, t.dz) != (32, 8, 16)  # the built-in default, not the stale tile
+    st, rep = _tune_from_cache_only(ctx, cache)
+    assert st == p.EDEVICE and rep.from_cache == 0
+    p.stencil_destroy(ctx)
+    # The same entry under this build's id is taken by both.
+    with open(cache, "a") as f:
+        f.write(_entry(good))
+    ctx = _init(nx=64, ny=48, nz=40, device=1000)
+    t = p.stencil_get_tile(ctx)
+    assert (t.bx, t.by, t.dz) == (32, 8, 16)
+    st, rep = _tune_from_cache_only(ctx, cache)
+    assert st == p.OK and rep.from_cache == 1 and (rep.tile.bx, rep.tile.by, rep.tile.dz) == (32, 8, 16)
     p.stencil_destroy(ctx)
 
 

@@ -1,8 +1,9 @@
 """GPU misfit gradient (adjoint steps + checkpointed forward) against the
 FP64 oracle's gradient, plus properties that hold at any size.
 
-Bars: gradient rel-L2 <= 1e-4 against the oracle's; misfit within 1e-4
-relative; the adjoint dot-product identity to FP32 accuracy at 256^3."""
+Bars: gradient rel-L2 <= 1e-4 against the oracle's (and its largest
+single-point deviation <= 1e-3 of its peak); misfit within 1e-4 relative;
+the adjoint dot-product identity to FP32 accuracy at 256^3."""
 import sys
 
 import numpy as np
@@ -10,6 +11,7 @@ import pytest
 import torch
 
 import oracle
+from compare import check_close
 from oracle import adjoint as oadj
 import paper_1310_8232_amd as p
 from paper_1310_8232_amd import adjoint
@@ -61,10 +63,40 @@ def test_gradient_vs_oracle(shape, nt, radius, every):
     J, g, _ = adjoint.misfit_gradient(prop, _survey(c), cuda(obs), checkpoint_every=every)
     torch.cuda.synchronize()
     J = float(J.item())
-    e = oracle.rel_l2(g.cpu().numpy(), g_ref)
-    log(f"  J gpu {J:.8e} oracle {J_ref:.8e}; gradient rel_l2 {e:.3e}")
+    log(f"  J gpu {J:.8e} oracle {J_ref:.8e}")
+    check_close(g.cpu().numpy(), g_ref, 1e-4, "gradient")
     assert abs(J - J_ref) <= 1e-4 * J_ref
-    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_gradient_config4_inputs(n):
+    # The gradient workload's own inputs: layered true model, current model
+    # with a -5% Gaussian blob (width n/8), 15 Hz Ricker, source and receiver
+    # line at z = 2R, 500 steps, checkpoints every 50. The observed data are
+    # each side's forward modelling of the true model (FP32 on the GPU, FP64
+    # in the oracle), as in a synthetic inversion. The residual is only 2-5%
+    # of the traces, but the rounding the GPU's two forward runs share (all
+    # of it until the wave meets the blob) cancels in it. Bar: rel-L2 <= 1e-4
+    # (per point: 1e-3 of the gradient's peak); misfit within 1e-4.
+    nt = 500
+    c = workloads.config_gradient(n, n, n, nt=nt)
+    log(f"case: gradient, config-4 inputs at {n}^3, {nt} steps, checkpoints every 50")
+    kap_true = oadj.kappa_from_slowness2(c["m_true"], c["dt"], c["h"])
+    obs_ref = oadj.traces(oadj.forward_all(kap_true, 4, nt, c["src_idx"], c["amp"]), c["rec_idx"])
+    J_ref, g_ref = oadj.misfit_and_gradient(c["m_cur"].astype(np.float64), c["dt"], c["h"], 4, nt,
+                                            c["src_idx"], c["amp"], c["rec_idx"], obs_ref)
+    survey = _survey(c)
+    prop_true = p.Propagator(cuda(c["m_true"]), c["h"], c["dt"], 4, slowness2=True)
+    obs, _, _ = adjoint.forward(prop_true, survey)
+    del prop_true
+    prop = p.Propagator(cuda(c["m_cur"]), c["h"], c["dt"], 4, slowness2=True)
+    J, g, tr = adjoint.misfit_gradient(prop, survey, obs, checkpoint_every=50)
+    torch.cuda.synchronize()
+    J = float(J.item())
+    tr_ref_norm = float(np.linalg.norm(obs_ref)) or 1.0
+    log(f"  residual / traces {np.sqrt(2.0 * J_ref) / tr_ref_norm:.3e}; J gpu {J:.8e} oracle {J_ref:.8e}")
+    check_close(g.cpu().numpy(), g_ref, 1e-4, "gradient")
+    assert abs(J - J_ref) <= 1e-4 * J_ref
 
 
 def test_checkpoint_interval_does_not_change_bits():

@@ -1,7 +1,8 @@
 """GPU parity: the gfx950 path (through the C ABI) against the FP64 oracle.
 
 Bars: relative L2 <= 1e-5 per output against the FP64 oracle (FP32 storage and
-arithmetic); bit-identical outputs across every tile shape, march depth, XCD
+arithmetic), and the largest single-point deviation <= 1e-4 of the field's
+peak; bit-identical outputs across every tile shape, march depth, XCD
 order and the plain-tiling kernel (all use one canonical FP32 operation
 order); kappa bit-identical to the FP64 formula rounded once.
 """
@@ -16,6 +17,7 @@ import torch
 import oracle
 import workloads
 import paper_1310_8232_amd as p
+from compare import check_close
 
 pytestmark = pytest.mark.gpu
 
@@ -63,10 +65,9 @@ def oracle_run(v, h, dt, R, nt, u0=None, um1=None, src_idx=None, amp=None, it0=0
 
 
 def assert_close(got, ref, tol=TOL, what=""):
-    e = oracle.rel_l2(got, ref)
-    log(f"  {what} rel_l2 = {e:.3e}")
-    assert np.all(np.isfinite(got))
-    assert e <= tol, f"{what}: rel_l2 {e:.3e} > {tol:.1e}"
+    # rel-L2 over the field and the largest single-point deviation (bound:
+    # ten times the rel-L2 bar; see tests/compare.py).
+    check_close(got, ref, tol, what)
 
 
 def test_kappa_bit_exact():
@@ -309,12 +310,12 @@ def test_full_size_512_tuned_default_plain():
             assert np.array_equal(un, base[0]) and np.array_equal(unm1, base[1])
 
 
-def _throughput_workload_vs_oracle(nt):
-    # The throughput workload exactly as the bench runs it (512^3 layered
+def _throughput_workload_vs_oracle(nt, n=512):
+    # The throughput workload exactly as the bench runs it (n^3 layered
     # model, source at the centre, from rest), with a searched tile, against
     # the FP64 oracle after nt steps.
-    c = workloads.config_layered(512, 512, 512, nt=nt)
-    log(f"case: 512^3 throughput workload from rest, searched tile, {nt} steps vs oracle")
+    c = workloads.config_layered(n, n, n, nt=nt)
+    log(f"case: {n}^3 throughput workload from rest, searched tile, {nt} steps vs oracle")
     prop = p.Propagator(cuda(c["v"]), c["h"], c["dt"], 4, vmax=c["vmax"])
     rep, _, _ = prop.tune(n_iter=10, n_rep=3)  # the bench's search: every compiled tile
     tile = prop.tile
@@ -337,10 +338,63 @@ def _throughput_workload_vs_oracle(nt):
 
 @pytest.mark.slow
 def test_throughput_workload_512_100_steps():
-    (e1, e2), (un, unm1, _, _) = _throughput_workload_vs_oracle(100)
-    log(f"  u^100 rel_l2 {e1:.3e}   u^99 rel_l2 {e2:.3e}")
-    assert np.all(np.isfinite(un)) and np.all(np.isfinite(unm1))
-    assert e1 <= TOL and e2 <= TOL
+    _, (un, unm1, ref_n, ref_nm1) = _throughput_workload_vs_oracle(100)
+    assert_close(un, ref_n, what="u^100")
+    assert_close(unm1, ref_nm1, what="u^99")
+
+
+@pytest.mark.slow
+def test_throughput_workload_256_1000_steps():
+    # The throughput recipe for 1000 steps on a grid the FP64 oracle finishes
+    # in about a minute. FP32 rounding grows about linearly with the step
+    # count (rel-L2 <= 1e-5 holds at 100 steps), so 2e-4 bounds 1000 steps
+    # with a factor-of-two margin; the per-point bound is ten times that.
+    _, (un, unm1, ref_n, ref_nm1) = _throughput_workload_vs_oracle(1000, n=256)
+    assert_close(un, ref_n, tol=2e-4, what="u^1000")
+    assert_close(unm1, ref_nm1, tol=2e-4, what="u^999")
+
+
+def _energy(u_next, u_cur, kap):
+    # Discrete energy of the source-free leapfrog scheme between levels n and
+    # n+1: sum (u^{n+1} - u^n)^2 / kappa - <u^{n+1}, L u^n>, in FP64; with L
+    # symmetric it is the same at every n.
+    u1 = u_next.astype(np.float64)
+    u0 = u_cur.astype(np.float64)
+    d = u1 - u0
+    return float(np.sum(d * d / kap)) - float(np.sum(u1 * oracle.laplacian(u0, 4)))
+
+
+@pytest.mark.slow
+def test_throughput_workload_512_1000_steps_energy():
+    # The bench's workload for 1000 steps on the searched tile, checked by a
+    # property that holds at any size: once the Ricker wavelet has died out
+    # (it is below 1e-17 of its peak after 3 t0 = 200 ms, step 228), the
+    # discrete energy stays constant. FP32 rounding perturbs it by about
+    # eps/(omega dt) = 6e-8/0.083 = 7e-7 relative per step, coherent at worst
+    # over the 700 steps checked: 5e-4; the bound is 1e-3.
+    c = workloads.config_layered(512, 512, 512, nt=1000)
+    log("case: 512^3 throughput workload, 1000 steps, energy after the source")
+    prop = p.Propagator(cuda(c["v"]), c["h"], c["dt"], 4, vmax=c["vmax"])
+    prop.tune(n_iter=10, n_rep=3)
+    log(f"  tile {prop.tile.as_dict()}")
+    idx = cuda(c["src_idx"], torch.int64)
+    amp = cuda(c["amp"].reshape(-1, 1))
+    src = p.make_src(idx, amp)
+    a, b = torch.zeros_like(prop.kappa), torch.zeros_like(prop.kappa)
+    a, b = prop.run(a, b, 300, src)
+    torch.cuda.synchronize()
+    u300, u299 = a.cpu().numpy(), b.cpu().numpy()
+    a, b = prop.run(a, b, 700, src, it0=300)
+    torch.cuda.synchronize()
+    u1000, u999 = a.cpu().numpy(), b.cpu().numpy()
+    assert np.all(np.isfinite(u1000)) and np.all(np.isfinite(u999))
+    # The GPU's kappa: the FP64 formula rounded once to FP32 (bit-exact, tested).
+    kap = oracle.kappa(c["v"], c["dt"], c["h"]).astype(np.float32).astype(np.float64)
+    e300 = _energy(u300, u299, kap)
+    e1000 = _energy(u1000, u999, kap)
+    drift = abs(e1000 - e300) / abs(e300)
+    log(f"  energy at 299.5: {e300:.9e}, at 999.5: {e1000:.9e}, relative drift {drift:.3e}")
+    assert e300 > 0 and drift <= 1e-3
 
 
 @pytest.mark.slow
