@@ -15,10 +15,19 @@
  * paper's loop blocking (Section 3, Fig. 1(b)) becomes the workgroup tile;
  * its blocksize search (Sections 3.2-3.3, 3.6, 3.7) becomes stencil_tune.
  *
- * Data layout: every field is a contiguous array [nz][ny][nx] in device
- * memory, x unit-stride, point (z, y, x) at linear index (z*ny + y)*nx + x;
- * kappa and the gradient fields are FP32 / FP64, wavefields are in the
- * context's storage type (FP32 unless FP16/BF16 is chosen).
+ * Data layout: every field is a contiguous array [nz][ny][pitch] in device
+ * memory, x unit-stride, point (z, y, x) at linear index
+ * (z*ny + y)*pitch + x, where pitch = nx unless stencil_desc.pitch sets a
+ * longer row (caller-padded rows, e.g. to a multiple of 128 bytes so that
+ * every row starts on a cache line). Values x in [nx, pitch) of a row are
+ * padding: the sweeps neither read them as grid points nor write them; the
+ * element-wise calls (kappa, convert, gradient terms, max |u|) process them
+ * like any other value, so keep them finite (zero). Source and receiver
+ * indices are linear indices of this layout; one that falls in padding is
+ * skipped (sources) or samples 0 (receivers). kappa and the gradient fields
+ * are FP32 / FP64, wavefields are in the context's storage type (FP32 unless
+ * FP16/BF16 is chosen). Sizes below ("of the grid's shape") mean
+ * pitch*ny*nz values.
  *
  * Ownership: field pointers are borrowed device memory (e.g. torch tensors);
  * the library never allocates, frees or retains them. A context owns only
@@ -86,7 +95,7 @@ typedef struct {
     int32_t ry;     /* rows per thread along y (ZMARCH) */
     int32_t dz;     /* planes per workgroup along z (ZMARCH); threads along z (PLAIN) */
     int32_t vw;     /* x points per thread: 8 (ZMARCH, 16-bit storage), 4, 2 (ZMARCH, FP32
-                       storage) or 1; must divide nx; 0 = the widest that divides nx */
+                       storage) or 1; must divide nx and the pitch; 0 = the widest that does */
     int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
     int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2) */
 } stencil_tile;
@@ -102,6 +111,8 @@ typedef struct {
     stencil_tile tile;    /* kind 0 = tune cache entry if any, else the built-in default */
     double storage_scale; /* wavefields are stored as storage_scale * u; a power of two (0 = 1).
                              The scheme is linear, so only source amplitudes are multiplied by it. */
+    int64_t pitch;        /* row stride in values: 0 = nx, else >= nx (padded rows). Vector tiles
+                             need vw to divide the pitch as well as nx. */
 } stencil_desc;
 
 /* Point sources (all device memory, borrowed): idx[n] linear indices,

@@ -57,7 +57,8 @@ class StencilDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
                 ("radius", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("h", ctypes.c_double), ("dt", ctypes.c_double), ("vmax", ctypes.c_double),
-                ("device", ctypes.c_int32), ("tile", StencilTile), ("storage_scale", ctypes.c_double)]
+                ("device", ctypes.c_int32), ("tile", StencilTile), ("storage_scale", ctypes.c_double),
+                ("pitch", ctypes.c_int64)]
 
 
 class StencilSrc(ctypes.Structure):
@@ -181,11 +182,12 @@ def make_tile(kind=TILE_ZMARCH, bx=0, by=0, ry=1, dz=0, vw=0, xcd=1, pf=0) -> St
 
 
 def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile | None = None, storage=F32,
-                 storage_scale: float = 1.0):
-    """Create a context; returns an opaque handle (int)."""
+                 storage_scale: float = 1.0, pitch: int = 0):
+    """Create a context; returns an opaque handle (int). pitch = 0: rows of nx
+    values; else the row stride of every field (>= nx)."""
     st = STORAGES[storage] if isinstance(storage, str) else int(storage)
     d = StencilDesc(nx, ny, nz, radius, st, h, dt, vmax, device, tile if tile is not None else StencilTile(),
-                    storage_scale)
+                    storage_scale, int(pitch))
     out = _vp()
     _check(_lib.stencil_init(ctypes.byref(d), ctypes.byref(out)))
     return out.value
@@ -452,11 +454,17 @@ class Propagator:
     ``v`` is a float32 CUDA tensor [nz, ny, nx]; kappa = (v dt / h)^2 is formed
     on the device by the library. The time loop alternates the two wavefield
     buffers: step n reads (u^n, u^{n-1}) and overwrites the u^{n-1} buffer
-    with u^{n+1}."""
+    with u^{n+1}.
+
+    ``pitch``: None for rows of nx values; an integer >= nx, or "align" (nx
+    rounded up to 128 bytes), stores every field as [nz, ny, pitch] with zero
+    padding at the end of each row. Fields passed in and returned then have
+    that shape (``store_shape``); ``grid(u)`` is the [nz, ny, nx] view of the
+    grid points and ``index(z, y, x)`` the linear index of a point."""
 
     def __init__(self, v, h: float, dt: float, radius: int = 4, vmax: float | None = None,
                  tile: StencilTile | None = None, slowness2: bool = False, storage="f32",
-                 storage_scale: float = 1.0):
+                 storage_scale: float = 1.0, pitch=None):
         import torch
         if v.dtype != torch.float32 or not v.is_cuda or v.dim() != 3 or not v.is_contiguous():
             raise ValueError("the model must be a contiguous float32 CUDA tensor [nz, ny, nx]")
@@ -469,8 +477,19 @@ class Propagator:
         self.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
         self.storage_scale = float(storage_scale)
         self.dtype = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}[self.storage]
+        if pitch == "align":
+            per_line = 128 // (4 if self.storage == F32 else 2)
+            pitch = -(-nx // per_line) * per_line
+        self.pitch = int(pitch) if pitch else nx
+        self.store_shape = (nz, ny, self.pitch)
         self.ctx = stencil_init(nx, ny, nz, h, dt, vmax, radius, v.device.index or 0, tile, self.storage,
-                                storage_scale)
+                                storage_scale, self.pitch if self.pitch != nx else 0)
+        if self.pitch != nx:
+            vp = torch.zeros(self.store_shape, dtype=torch.float32, device=self.device)
+            vp[..., :nx] = v
+            if slowness2:
+                vp[..., nx:] = 1.0  # any finite positive value; padding is never a grid point
+            v = vp
         self.kappa = torch.empty_like(v)
         if slowness2:
             stencil_kappa_slowness2(self.ctx, v, self.kappa)
@@ -484,25 +503,33 @@ class Propagator:
             self.ctx = None
 
     def _check_field(self, t):
-        if t.dtype != self.dtype or not t.is_cuda or tuple(t.shape) != self.shape or not t.is_contiguous():
-            raise ValueError(f"fields must be contiguous {self.dtype} CUDA tensors of shape {self.shape}")
+        if t.dtype != self.dtype or not t.is_cuda or tuple(t.shape) != self.store_shape or not t.is_contiguous():
+            raise ValueError(f"fields must be contiguous {self.dtype} CUDA tensors of shape {self.store_shape}")
 
     def zeros(self):
-        """A zero wavefield in the storage type."""
+        """A zero wavefield in the storage type (padding included)."""
         import torch
-        return torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+        return torch.zeros(self.store_shape, dtype=self.dtype, device=self.device)
+
+    def grid(self, u):
+        """The [nz, ny, nx] view of a field's grid points (no copy)."""
+        return u[..., : self.shape[2]]
+
+    def index(self, z: int, y: int, x: int) -> int:
+        """Linear index of grid point (z, y, x) in the stored layout."""
+        return (z * self.shape[1] + y) * self.pitch + x
 
     def to_storage(self, u32):
         """storage_scale * u rounded to the storage type (device kernel)."""
         import torch
-        out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        out = torch.empty(self.store_shape, dtype=self.dtype, device=self.device)
         stencil_convert(self.ctx, u32.contiguous(), out, True)
         return out
 
     def to_f32(self, u):
         """FP32 u from a stored wavefield (device kernel)."""
         import torch
-        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        out = torch.empty(self.store_shape, dtype=torch.float32, device=self.device)
         stencil_convert(self.ctx, u, out, False)
         return out
 

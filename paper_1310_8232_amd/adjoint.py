@@ -60,7 +60,7 @@ def forward(prop: Propagator, survey: Survey, checkpoint_every: int = 0, keep_le
     nt = survey.nt
     src = survey.src()
     if keep_levels:
-        levels = torch.empty((nt + 2,) + tuple(prop.shape), device=prop.device)
+        levels = torch.empty((nt + 2,) + tuple(prop.store_shape), device=prop.device)
         levels[0].zero_()
         levels[1].zero_()
         traces = torch.empty((nt, survey.rec_idx.numel()), device=prop.device)
@@ -68,8 +68,8 @@ def forward(prop: Propagator, survey: Survey, checkpoint_every: int = 0, keep_le
             stencil_step_to(prop.ctx, prop.kappa, levels[n + 1], levels[n], levels[n + 2], n, src)
             stencil_sample(prop.ctx, levels[n + 2], survey.rec_idx, traces[n])
         return traces, {"levels": levels}, (levels[nt + 1], levels[nt])
-    a = torch.zeros(prop.shape, device=prop.device)
-    b = torch.zeros(prop.shape, device=prop.device)
+    a = torch.zeros(prop.store_shape, device=prop.device)
+    b = torch.zeros(prop.store_shape, device=prop.device)
     traces = torch.empty((nt, survey.rec_idx.numel()), device=prop.device)
     ckpts = {}
     for n in range(nt):
@@ -93,16 +93,16 @@ def misfit(traces: torch.Tensor, observed: torch.Tensor):
 
 
 def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict, checkpoint_every: int):
-    """Adjoint pass: returns dJ/dm (float64, the grid's shape)."""
+    """Adjoint pass: returns dJ/dm (float64, in the stored layout: prop.grid() gives the grid points)."""
     nt = survey.nt
     C = checkpoint_every
     src = survey.src()
     rsrc = make_src(survey.rec_idx, resid)
-    grad = torch.zeros(prop.shape, dtype=torch.float64, device=prop.device)
+    grad = torch.zeros(prop.store_shape, dtype=torch.float64, device=prop.device)
     # Four buffers of mu: the pair (mu^{k+1}, mu^{k+2}) that the next adjoint
     # step reads, and room for up to four new levels whose gradient terms are
     # then added in one pass.
-    bufs = [torch.zeros(prop.shape, device=prop.device) for _ in range(4)]
+    bufs = [torch.zeros(prop.store_shape, device=prop.device) for _ in range(4)]
     state = [bufs[0], bufs[1]]  # [mu^{k+1}, mu^{k+2}]
 
     def adjoint_range(k_hi, k_lo, level):
@@ -128,7 +128,7 @@ def backward(prop: Propagator, survey: Survey, resid: torch.Tensor, ckpts: dict,
         L = ckpts["levels"]  # L[n + 1] = u^n
         adjoint_range(nt, 0, lambda j: L[j + 1])
         return grad
-    buf = torch.empty((C,) + tuple(prop.shape), device=prop.device)
+    buf = torch.empty((C,) + tuple(prop.store_shape), device=prop.device)
     for n0 in sorted(ckpts, reverse=True):
         n1 = min(n0 + C, nt)
         u0, um1 = ckpts[n0]

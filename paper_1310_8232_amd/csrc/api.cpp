@@ -24,6 +24,7 @@ using p1310::ZVariant;
 
 struct stencil_ctx {
     stencil_desc d;
+    int64_t pitch = 0;     // row stride in values (d.pitch, or nx when that is 0)
     int R = 4;
     int st = p1310::kF32;  // wavefield storage
     int es = 4;            // bytes per wavefield value
@@ -175,9 +176,14 @@ stencil_status fail(stencil_ctx *ctx, stencil_status st, const std::string &msg)
 
 size_t round256(size_t n) { return (n + 255) / 256 * 256; }
 
-int64_t npoints(const stencil_ctx *c) { return c->d.nx * c->d.ny * c->d.nz; }
+// Values of one field as stored: pitch * ny * nz (the padding included).
+int64_t nstore(const stencil_ctx *c) { return c->pitch * c->d.ny * c->d.nz; }
 
-bool vec4_ok(const stencil_ctx *c) { return c->d.nx % 4 == 0; }
+// A vector of vw values must neither straddle the end of a row's grid points
+// nor leave the row's alignment: vw divides nx and the pitch.
+bool vw_fits(const stencil_ctx *c, int vw) { return c->d.nx % vw == 0 && c->pitch % vw == 0; }
+
+bool vec4_ok(const stencil_ctx *c) { return vw_fits(c, 4); }
 
 bool has_vw(const stencil_ctx *ctx, int vw)
 {
@@ -191,9 +197,9 @@ bool has_vw(const stencil_ctx *ctx, int vw)
 // Widest x vector that divides nx and has compiled one-step kernels.
 int auto_vw(const stencil_ctx *ctx)
 {
-    if (ctx->d.nx % 8 == 0 && has_vw(ctx, 8)) return 8;
-    if (ctx->d.nx % 4 == 0) return 4;
-    if (ctx->d.nx % 2 == 0 && has_vw(ctx, 2)) return 2;
+    if (vw_fits(ctx, 8) && has_vw(ctx, 8)) return 8;
+    if (vw_fits(ctx, 4)) return 4;
+    if (vw_fits(ctx, 2) && has_vw(ctx, 2)) return 2;
     return 1;
 }
 
@@ -251,13 +257,13 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     }
     if (t.kind == STENCIL_TILE_ZMARCH2) {
         if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
-        if (t.vw < 1 || d.nx % t.vw) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx");
+        if (t.vw < 1 || !vw_fits(ctx, t.vw)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx and the pitch");
         t.ry = 1;
         const Z2Variant *v = find_variant2(ctx, t);
         if (!v) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled two-step kernel for this (bx, by, vw), radius, storage");
         if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
         if (t.dz > d.nz) t.dz = (int32_t)d.nz;
-        if ((t.dz + 4 * ctx->R) * d.nx * d.ny * 4 >= kWindowLimit)
+        if ((t.dz + 4 * ctx->R) * ctx->pitch * d.ny * 4 >= kWindowLimit)
             return fail(ctx, STENCIL_EUNSUPPORTED, "two-step window (dz + 4R planes) must stay below 2 GiB; lower dz");
         const int64_t gx = (d.nx + v->own_x - 1) / v->own_x, gy = (d.ny + v->own_y - 1) / v->own_y;
         if (!launch_fits(gx * gy * ((d.nz + t.dz - 1) / t.dz), v->threads))
@@ -268,12 +274,12 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     }
     if (t.kind != STENCIL_TILE_ZMARCH) return fail(ctx, STENCIL_EUNSUPPORTED, "unknown tile kind");
     if (t.vw == 0) t.vw = auto_vw(ctx);
-    if (t.vw < 1 || d.nx % t.vw) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx");
+    if (t.vw < 1 || !vw_fits(ctx, t.vw)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx and the pitch");
     const ZVariant *zv = find_variant(ctx, t);
     if (!zv) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled z-march kernel for this (bx, by, ry, vw, pf) and radius");
     if (t.dz < 1) return fail(ctx, STENCIL_EUNSUPPORTED, "dz must be >= 1");
     if (t.dz > d.nz) t.dz = (int32_t)d.nz;
-    const int64_t plane_bytes = d.nx * d.ny * 4;
+    const int64_t plane_bytes = ctx->pitch * d.ny * 4;
     if ((t.dz + 2 * ctx->R) * plane_bytes >= kWindowLimit)
         return fail(ctx, STENCIL_EUNSUPPORTED, "z-march window (dz + 2R planes) must stay below 2 GiB; lower dz");
     const int64_t gx = (d.nx + (int64_t)t.bx * t.vw - 1) / ((int64_t)t.bx * t.vw);
@@ -288,13 +294,13 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
 
 bool zmarch_possible(const stencil_ctx *ctx)
 {
-    return (1 + 2 * ctx->R) * ctx->d.nx * ctx->d.ny * 4 < kWindowLimit;
+    return (1 + 2 * ctx->R) * ctx->pitch * ctx->d.ny * 4 < kWindowLimit;
 }
 
 // Deepest march whose window of dz + halo_planes planes stays below 2 GiB.
 int32_t max_dz(const stencil_ctx *ctx, int halo_planes)
 {
-    const int64_t plane_bytes = ctx->d.nx * ctx->d.ny * 4;
+    const int64_t plane_bytes = ctx->pitch * ctx->d.ny * 4;
     const int64_t dz = (kWindowLimit - 1) / plane_bytes - halo_planes;
     return dz < 1 ? 0 : (int32_t)std::min<int64_t>(dz, 1 << 30);
 }
@@ -377,7 +383,8 @@ stencil_tile default_tile2(const stencil_ctx *ctx)
 
 // --------------------------------------------------------------------------
 // Tune cache: one line per entry,
-//   v2 <build id> R<r> <storage> <nx> <ny> <nz> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms> <actual_ms>
+//   v2 <build id> R<r> <storage> <nx> <ny> <nz> <pitch> <kind> <bx> <by> <ry> <dz> <vw> <xcd> <pf> <min_ms>
+//   <actual_ms>
 // where the build id (stencil_build_id) names the offload architecture, the
 // HIP version the kernels were compiled with, the HIP runtime in use and a
 // hash of the kernel and runtime sources. An entry measured with other code
@@ -415,15 +422,16 @@ bool cache_lookup(const char *path, const stencil_ctx *ctx, bool two, stencil_ti
     static const char *kst[] = {"f32", "f16", "bf16"};
     while (std::fgets(line, sizeof line, f)) {
         char ver[8], id[160], rr[8], dt[8];
-        long long nx, ny, nz;
+        long long nx, ny, nz, pitch;
         stencil_tile c = {};
         double a = 0, b = 0;
-        int n = std::sscanf(line, "%7s %159s %7s %7s %lld %lld %lld %d %d %d %d %d %d %d %d %lf %lf", ver, id, rr, dt,
-                            &nx, &ny, &nz, &c.kind, &c.bx, &c.by, &c.ry, &c.dz, &c.vw, &c.xcd, &c.pf, &a, &b);
-        if (n != 17) continue;
+        int n = std::sscanf(line, "%7s %159s %7s %7s %lld %lld %lld %lld %d %d %d %d %d %d %d %d %lf %lf", ver, id, rr,
+                            dt, &nx, &ny, &nz, &pitch, &c.kind, &c.bx, &c.by, &c.ry, &c.dz, &c.vw, &c.xcd, &c.pf, &a,
+                            &b);
+        if (n != 18) continue;
         if (std::strcmp(ver, "v2") || build_id() != id) continue;
         if (std::strcmp(rr, want) || std::strcmp(dt, kst[ctx->st])) continue;
-        if (nx != ctx->d.nx || ny != ctx->d.ny || nz != ctx->d.nz) continue;
+        if (nx != ctx->d.nx || ny != ctx->d.ny || nz != ctx->d.nz || pitch != ctx->pitch) continue;
         if ((c.kind == STENCIL_TILE_ZMARCH2) != two) continue;
         *t = c;
         *mn = a;
@@ -440,9 +448,9 @@ void cache_store(const char *path, const stencil_ctx *ctx, const stencil_tile &t
     FILE *f = std::fopen(path, "a");
     if (!f) return;
     static const char *kst[] = {"f32", "f16", "bf16"};
-    std::fprintf(f, "v2 %s R%d %s %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", build_id().c_str(), ctx->R,
-                 kst[ctx->st], (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz, t.kind, t.bx, t.by,
-                 t.ry, t.dz, t.vw, t.xcd, t.pf, mn, act);
+    std::fprintf(f, "v2 %s R%d %s %lld %lld %lld %lld %d %d %d %d %d %d %d %d %.6f %.6f\n", build_id().c_str(),
+                 ctx->R, kst[ctx->st], (long long)ctx->d.nx, (long long)ctx->d.ny, (long long)ctx->d.nz,
+                 (long long)ctx->pitch, t.kind, t.bx, t.by, t.ry, t.dz, t.vw, t.xcd, t.pf, mn, act);
     std::fclose(f);
 }
 
@@ -491,6 +499,7 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
     a.uprev = uprev;
     a.unext = unext;
     a.nx = (int)d.nx;
+    a.pitch = (int)ctx->pitch;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
     for (int m = 0; m <= ctx->R; ++m) a.c[m] = ctx->cf[m];
@@ -515,7 +524,8 @@ hipError_t enqueue_step(const stencil_ctx *ctx, const stencil_tile &t, const flo
     }
     if (e != hipSuccess) return e;
     if (nsrc > 1)
-        e = p1310::launch_inject(ctx->st, unext, kappa, npoints(ctx), src->idx, src->amp, nsrc, it, ctx->scale, s);
+        e = p1310::launch_inject(ctx->st, unext, kappa, nstore(ctx), ctx->pitch, ctx->d.nx, src->idx, src->amp, nsrc,
+                                 it, ctx->scale, s);
     return e;
 }
 
@@ -681,6 +691,7 @@ hipError_t enqueue_step2(const stencil_ctx *ctx, const stencil_tile &t, const fl
     a.unext = unext;
     a.unext2 = unext2;
     a.nx = (int)d.nx;
+    a.pitch = (int)ctx->pitch;
     a.ny = (int)d.ny;
     a.nz = (int)d.nz;
     for (int m = 0; m <= ctx->R; ++m) a.c[m] = ctx->cf[m];
@@ -780,7 +791,9 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     if (!d || !out) return STENCIL_EINVAL;
     if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 0x7fffffff || d->ny > 0x7fffffff || d->nz > 0x7fffffff)
         return STENCIL_EINVAL;
-    if (d->nx * d->ny > ((int64_t)1 << 29)) return STENCIL_EINVAL;  // plane byte offsets are 32-bit
+    if (d->pitch != 0 && (d->pitch < d->nx || d->pitch > 0x7fffffff)) return STENCIL_EINVAL;
+    const int64_t pitch = d->pitch ? d->pitch : d->nx;
+    if (pitch * d->ny > ((int64_t)1 << 29)) return STENCIL_EINVAL;  // plane byte offsets are 32-bit
     if (!radius_ok(d->radius)) return STENCIL_EINVAL;
     if (d->storage != STENCIL_F32 && d->storage != STENCIL_F16 && d->storage != STENCIL_BF16)
         return STENCIL_EUNSUPPORTED;
@@ -799,6 +812,7 @@ stencil_status stencil_init(const stencil_desc *d, stencil_ctx **out)
     stencil_ctx *ctx = new (std::nothrow) stencil_ctx;
     if (!ctx) return STENCIL_ENOMEM;
     ctx->d = *d;
+    ctx->pitch = pitch;
     ctx->R = d->radius;
     ctx->st = d->storage;
     ctx->es = d->storage == STENCIL_F32 ? 4 : 2;
@@ -897,7 +911,7 @@ stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_
     if (!kappa || !u_cur || !u_prev || !u_next || !u_next2) return fail(ctx, STENCIL_EINVAL, "null field pointer");
     if (ctx->tile2.kind != STENCIL_TILE_ZMARCH2)
         return fail(ctx, STENCIL_EUNSUPPORTED, "no two-step kernel for this radius and storage");
-    const int64_t ub = npoints(ctx) * ctx->es, kb = npoints(ctx) * 4;
+    const int64_t ub = nstore(ctx) * ctx->es, kb = nstore(ctx) * 4;
     const void *f[] = {u_cur, u_prev, u_next, u_next2};
     for (int i = 0; i < 4; ++i) {
         if (overlaps2(kappa, kb, f[i], ub)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps a wavefield");
@@ -948,7 +962,7 @@ stencil_status stencil_kappa(stencil_ctx *ctx, const void *v, void *kappa, void 
     if (!v || !kappa) return fail(ctx, STENCIL_EINVAL, "null pointer");
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = p1310::launch_kappa((const float *)v, (float *)kappa, npoints(ctx), ctx->d.dt, ctx->d.h,
+    hipError_t e = p1310::launch_kappa((const float *)v, (float *)kappa, nstore(ctx), ctx->d.dt, ctx->d.h,
                                        (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "kappa launch");
     return STENCIL_OK;
@@ -959,7 +973,7 @@ stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!kappa || !u_cur || !u_prev || !u_next) return fail(ctx, STENCIL_EINVAL, "null field pointer");
-    const int64_t bytes = npoints(ctx) * ctx->es, kbytes = npoints(ctx) * 4;
+    const int64_t bytes = nstore(ctx) * ctx->es, kbytes = nstore(ctx) * 4;
     if (overlaps(u_cur, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "u_cur overlaps the output");
     if (overlaps2(kappa, kbytes, u_next, bytes)) return fail(ctx, STENCIL_EALIAS, "kappa overlaps the output");
     if (u_prev != u_next && overlaps(u_prev, u_next, bytes))
@@ -1066,7 +1080,7 @@ stencil_status stencil_tune(stencil_ctx *ctx, const void *kappa, void *scratch_a
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!kappa || !scratch_a || !scratch_b || !report) return fail(ctx, STENCIL_EINVAL, "null pointer");
-    const int64_t bytes = npoints(ctx) * ctx->es, kbytes = npoints(ctx) * 4;
+    const int64_t bytes = nstore(ctx) * ctx->es, kbytes = nstore(ctx) * 4;
     if (overlaps(scratch_a, scratch_b, bytes) || overlaps2(kappa, kbytes, scratch_a, bytes) ||
         overlaps2(kappa, kbytes, scratch_b, bytes))
         return fail(ctx, STENCIL_EALIAS, "kappa and the two scratch fields must not overlap");
@@ -1206,7 +1220,7 @@ stencil_status stencil_kappa_slowness2(stencil_ctx *ctx, const void *m, void *ka
     if (!m || !kappa) return fail(ctx, STENCIL_EINVAL, "null pointer");
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = p1310::launch_kappa_m((const float *)m, (float *)kappa, npoints(ctx), ctx->d.dt, ctx->d.h,
+    hipError_t e = p1310::launch_kappa_m((const float *)m, (float *)kappa, nstore(ctx), ctx->d.dt, ctx->d.h,
                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "kappa launch");
     return STENCIL_OK;
@@ -1222,7 +1236,8 @@ stencil_status stencil_sample(stencil_ctx *ctx, const void *u, const int64_t *id
     if (!u || !idx || !out) return fail(ctx, STENCIL_EINVAL, "null pointer");
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = p1310::launch_sample((const float *)u, npoints(ctx), idx, n, (float *)out, (hipStream_t)stream);
+    hipError_t e = p1310::launch_sample((const float *)u, nstore(ctx), ctx->pitch, ctx->d.nx, idx, n, (float *)out,
+                                        (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "sample launch");
     return STENCIL_OK;
 }
@@ -1236,7 +1251,7 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
     if (grad && (!u_next || !u_cur || !u_prev))
         return fail(ctx, STENCIL_EINVAL, "gradient accumulation needs u_next, u_cur and u_prev");
     if (grad) {
-        const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+        const int64_t fb = nstore(ctx) * 4, gb = nstore(ctx) * 8;
         const void *fields[] = {kappa, lam_cur, lam_prev_next, u_next, u_cur, u_prev};
         for (const void *f : fields)
             if (overlaps2(grad, gb, f, fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
@@ -1252,7 +1267,7 @@ stencil_status stencil_adjoint_step(stencil_ctx *ctx, const void *kappa, const v
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
     hipError_t e = p1310::launch_grad(grad, (const float *)lam_prev_next, (const float *)u_next, (const float *)u_cur,
-                                      (const float *)u_prev, npoints(ctx), scale, (hipStream_t)stream);
+                                      (const float *)u_prev, nstore(ctx), scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
     return STENCIL_OK;
 }
@@ -1264,7 +1279,7 @@ stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void 
     if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "the gradient needs FP32 storage");
     if (!mu_k || !mu_km1 || !u_k || !u_km1 || !u_km2 || !u_km3 || !grad)
         return fail(ctx, STENCIL_EINVAL, "null pointer");
-    const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+    const int64_t fb = nstore(ctx) * 4, gb = nstore(ctx) * 8;
     const void *fields[] = {mu_k, mu_km1, u_k, u_km1, u_km2, u_km3};
     for (const void *f : fields)
         if (overlaps2(grad, gb, f, fb)) return fail(ctx, STENCIL_EALIAS, "grad overlaps another field");
@@ -1273,7 +1288,7 @@ stencil_status stencil_gradient2(stencil_ctx *ctx, const void *mu_k, const void 
     const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
     const float *mu[] = {(const float *)mu_k, (const float *)mu_km1};
     const float *u[] = {(const float *)u_k, (const float *)u_km1, (const float *)u_km2, (const float *)u_km3};
-    hipError_t e = p1310::launch_gradn(2, grad, mu, u, npoints(ctx), scale, (hipStream_t)stream);
+    hipError_t e = p1310::launch_gradn(2, grad, mu, u, nstore(ctx), scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
     return STENCIL_OK;
 }
@@ -1285,7 +1300,7 @@ stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *c
     if (ctx->st != p1310::kF32) return fail(ctx, STENCIL_EUNSUPPORTED, "the gradient needs FP32 storage");
     if (m < 1 || m > 4) return fail(ctx, STENCIL_EINVAL, "m must be 1..4");
     if (!mu || !u || !grad) return fail(ctx, STENCIL_EINVAL, "null pointer");
-    const int64_t fb = npoints(ctx) * 4, gb = npoints(ctx) * 8;
+    const int64_t fb = nstore(ctx) * 4, gb = nstore(ctx) * 8;
     const float *fm[4], *fu[6];
     for (int j = 0; j < m; ++j) {
         if (!mu[j]) return fail(ctx, STENCIL_EINVAL, "null pointer");
@@ -1300,7 +1315,7 @@ stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *c
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
     const double scale = -(ctx->d.h * ctx->d.h) / (ctx->d.dt * ctx->d.dt);
-    hipError_t e = p1310::launch_gradn(m, grad, fm, fu, npoints(ctx), scale, (hipStream_t)stream);
+    hipError_t e = p1310::launch_gradn(m, grad, fm, fu, nstore(ctx), scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "gradient launch");
     return STENCIL_OK;
 }
@@ -1332,7 +1347,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             delete bt;
             return STENCIL_EINVAL;
         }
-        const int64_t ub = npoints(sh.ctx) * sh.ctx->es, kb = npoints(sh.ctx) * 4;
+        const int64_t ub = nstore(sh.ctx) * sh.ctx->es, kb = nstore(sh.ctx) * 4;
         if (overlaps(sh.u_a, sh.u_b, ub) || overlaps2(sh.kappa, kb, sh.u_a, ub) || overlaps2(sh.kappa, kb, sh.u_b, ub)) {
             delete bt;
             return STENCIL_EALIAS;
@@ -1350,7 +1365,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
         // overlap any field of another (kappa may be shared: it is only read).
         for (int j = 0; j < i; ++j) {
             const stencil_shot &o = shots[j];
-            const int64_t oub = npoints(o.ctx) * o.ctx->es, okb = npoints(o.ctx) * 4;
+            const int64_t oub = nstore(o.ctx) * o.ctx->es, okb = nstore(o.ctx) * 4;
             const void *mine[] = {sh.u_a, sh.u_b}, *theirs[] = {o.u_a, o.u_b};
             bool clash = false;
             for (const void *w : mine)
@@ -1398,6 +1413,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             SweepArgs a = {};
             a.kappa = sh.kappa;
             a.nx = (int)d.nx;
+            a.pitch = (int)sh.ctx->pitch;
             a.ny = (int)d.ny;
             a.nz = (int)d.nz;
             for (int m = 0; m <= sh.ctx->R; ++m) a.c[m] = sh.ctx->cf[m];
@@ -1496,7 +1512,8 @@ stencil_status stencil_batch_step(stencil_batch *bt, int64_t it, void *stream)
             hipError_t e = enqueue_step(sh.ctx, sh.tile, sh.kappa, uc, up, up, it, sh.src.n ? &sh.src : nullptr, s);
             if (e != hipSuccess) return STENCIL_EDEVICE;
         } else if (sh.src.n > 1) {
-            hipError_t e = p1310::launch_inject(sh.ctx->st, up, sh.kappa, npoints(sh.ctx), sh.src.idx, sh.src.amp,
+            hipError_t e = p1310::launch_inject(sh.ctx->st, up, sh.kappa, nstore(sh.ctx), sh.ctx->pitch, sh.ctx->d.nx,
+                                                sh.src.idx, sh.src.amp,
                                                 sh.src.n, it, sh.ctx->scale, s);
             if (e != hipSuccess) return STENCIL_EDEVICE;
         }
@@ -1638,12 +1655,12 @@ stencil_status stencil_convert(stencil_ctx *ctx, const void *src, void *dst, int
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!src || !dst) return fail(ctx, STENCIL_EINVAL, "null pointer");
-    const int64_t ub = npoints(ctx) * ctx->es, fb = npoints(ctx) * 4;
+    const int64_t ub = nstore(ctx) * ctx->es, fb = nstore(ctx) * 4;
     if (overlaps2(src, to_storage ? fb : ub, dst, to_storage ? ub : fb))
         return fail(ctx, STENCIL_EALIAS, "src and dst overlap");
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = p1310::launch_convert(ctx->st, src, dst, npoints(ctx), ctx->scale, to_storage ? 1 : 0,
+    hipError_t e = p1310::launch_convert(ctx->st, src, dst, nstore(ctx), ctx->scale, to_storage ? 1 : 0,
                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "convert launch");
     return STENCIL_OK;
@@ -1663,10 +1680,10 @@ stencil_status stencil_max_abs(stencil_ctx *ctx, const void *u, float *out, void
 {
     if (!ctx) return STENCIL_EINVAL;
     if (!u || !out) return fail(ctx, STENCIL_EINVAL, "null pointer");
-    if (overlaps2(out, 4, u, npoints(ctx) * ctx->es)) return fail(ctx, STENCIL_EALIAS, "out lies inside the field");
+    if (overlaps2(out, 4, u, nstore(ctx) * ctx->es)) return fail(ctx, STENCIL_EALIAS, "out lies inside the field");
     DeviceGuard g(ctx->d.device);
     if (g.status != hipSuccess) return hip_fail(ctx, g.status, "hipSetDevice");
-    hipError_t e = p1310::launch_max_abs(ctx->st, u, npoints(ctx), (unsigned int *)out, (hipStream_t)stream);
+    hipError_t e = p1310::launch_max_abs(ctx->st, u, nstore(ctx), (unsigned int *)out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "max_abs launch");
     return STENCIL_OK;
 }

@@ -18,6 +18,7 @@ struct SweepArgs {
     void *unext;             // u^{n+1} (may be uprev: in-place update)
     void *unext2;            // u^{n+2} (two-step kernels only)
     int nx, ny, nz;
+    int pitch;               // row stride in values (>= nx); point (z,y,x) at (z*ny + y)*pitch + x
     int dz;                  // planes per workgroup (z-march)
     int gx, gy, gz;          // tiles along x, y and z-chunks
     int xcd;                 // 0 = linear workgroup order, else number of XCDs to spread over
@@ -63,13 +64,16 @@ hipError_t launch_zmarch(const ZVariant &v, const SweepArgs &a, hipStream_t s);
 hipError_t launch_zmarch_batch(const ZVariant &v, const SweepArgs *shots, const int *wg_begin, int nshots,
                                int total_blocks, int xcd, int64_t it, hipStream_t s);
 hipError_t launch_plain(int R, int st, int bx, int by, int bz, const SweepArgs &a, hipStream_t s);
-hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, const int64_t *idx,
-                         const float *amp, int nsrc, int64_t it, float scale, hipStream_t s);
+// Sources whose index is outside [0, n_points) or falls in a row's padding
+// (index mod pitch >= nx) are skipped.
+hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, int64_t pitch, int64_t nx,
+                         const int64_t *idx, const float *amp, int nsrc, int64_t it, float scale, hipStream_t s);
 hipError_t launch_convert(int st, const void *src, void *dst, int64_t n, float scale, int to_storage,
                           hipStream_t s);
 hipError_t launch_kappa(const float *v, float *kappa, int64_t n, double dt, double h, hipStream_t s);
 hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, double h, hipStream_t s);
-hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s);
+hipError_t launch_sample(const float *u, int64_t n_points, int64_t pitch, int64_t nx, const int64_t *idx, int n,
+                         float *out, hipStream_t s);
 hipError_t launch_grad(double *g, const float *mu, const float *un, const float *uc, const float *up, int64_t n,
                        double scale, hipStream_t s);
 // m = 1..4 consecutive gradient terms: mu[0..m-1], u[0..m+1] (see gradn_kernel).

@@ -97,15 +97,18 @@ __device__ __forceinline__ uint32_t inject_slot(uint64_t q, uint32_t mask)
 }
 
 template <typename ST>
-__global__ void __launch_bounds__(256) inject_kernel(ST *u, const float *kappa, int64_t n_points, const int64_t *idx,
-                                                     const float *amp, int nsrc, int64_t it, float scale)
+__global__ void __launch_bounds__(256) inject_kernel(ST *u, const float *kappa, int64_t n_points, int64_t pitch,
+                                                     int64_t nx, const int64_t *idx, const float *amp, int nsrc,
+                                                     int64_t it, float scale)
 {
+    // A grid point: inside the array and not in a row's padding.
+    auto on_grid = [&](int64_t q) { return q >= 0 && q < n_points && (pitch == nx || q % pitch < nx); };
     __shared__ unsigned long long keys[kInjectSlots];
     __shared__ int kfirst[kInjectSlots], klast[kInjectSlots], kcount[kInjectSlots];
     const unsigned long long kEmpty = ~0ull;  // no grid index (they are >= 0)
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t p = j < nsrc ? idx[j] : -1;
-    bool owner = p >= 0 && p < n_points;
+    bool owner = on_grid(p);
     float kp = 0.0f, v = 0.0f;
     if (owner) {
         kp = kappa[p];
@@ -127,7 +130,7 @@ __global__ void __launch_bounds__(256) inject_kernel(ST *u, const float *kappa, 
         __syncthreads();
         for (int t = threadIdx.x; t < cn; t += blockDim.x) {
             const int64_t q = idx[c0 + t];
-            if (q < 0 || q >= n_points) continue;
+            if (!on_grid(q)) continue;
             uint32_t h = inject_slot((uint64_t)q, mask);
             for (int probe = 0; probe < H; ++probe) {  // H >= 2 cn: a free slot exists
                 const unsigned long long prev = atomicCAS(&keys[h], kEmpty, (unsigned long long)q);
@@ -182,13 +185,13 @@ __global__ void __launch_bounds__(256) convert_kernel(const void *src, void *dst
 }
 
 // Receiver samples: out[j] = u[idx[j]] (0 for an index outside the grid).
-__global__ void __launch_bounds__(256) sample_kernel(const float *u, int64_t n_points, const int64_t *idx, int n,
-                                                     float *out)
+__global__ void __launch_bounds__(256) sample_kernel(const float *u, int64_t n_points, int64_t pitch, int64_t nx,
+                                                     const int64_t *idx, int n, float *out)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     const int64_t p = idx[j];
-    out[j] = (p >= 0 && p < n_points) ? u[p] : 0.0f;
+    out[j] = (p >= 0 && p < n_points && (pitch == nx || p % pitch < nx)) ? u[p] : 0.0f;
 }
 
 // Gradient accumulation (FP64): g += s * mu * (u^{k} - 2 u^{k-1} + u^{k-2}).
@@ -473,22 +476,22 @@ hipError_t launch_plain(int R, int st, int bx, int by, int bz, const SweepArgs &
     }
 }
 
-hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, const int64_t *idx,
-                         const float *amp, int nsrc, int64_t it, float scale, hipStream_t s)
+hipError_t launch_inject(int st, void *u, const float *kappa, int64_t n_points, int64_t pitch, int64_t nx,
+                         const int64_t *idx, const float *amp, int nsrc, int64_t it, float scale, hipStream_t s)
 {
     const dim3 grid((nsrc + 255) / 256), block(256);
     switch (st) {
     case kF32:
-        hipLaunchKernelGGL(inject_kernel<float>, grid, block, 0, s, (float *)u, kappa, n_points, idx, amp, nsrc, it,
-                           scale);
-        break;
-    case kF16:
-        hipLaunchKernelGGL(inject_kernel<_Float16>, grid, block, 0, s, (_Float16 *)u, kappa, n_points, idx, amp,
+        hipLaunchKernelGGL(inject_kernel<float>, grid, block, 0, s, (float *)u, kappa, n_points, pitch, nx, idx, amp,
                            nsrc, it, scale);
         break;
+    case kF16:
+        hipLaunchKernelGGL(inject_kernel<_Float16>, grid, block, 0, s, (_Float16 *)u, kappa, n_points, pitch, nx, idx,
+                           amp, nsrc, it, scale);
+        break;
     case kBF16:
-        hipLaunchKernelGGL(inject_kernel<__bf16>, grid, block, 0, s, (__bf16 *)u, kappa, n_points, idx, amp, nsrc,
-                           it, scale);
+        hipLaunchKernelGGL(inject_kernel<__bf16>, grid, block, 0, s, (__bf16 *)u, kappa, n_points, pitch, nx, idx, amp,
+                           nsrc, it, scale);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -527,9 +530,10 @@ hipError_t launch_kappa_m(const float *m, float *kappa, int64_t n, double dt, do
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const float *u, int64_t n_points, const int64_t *idx, int n, float *out, hipStream_t s)
+hipError_t launch_sample(const float *u, int64_t n_points, int64_t pitch, int64_t nx, const int64_t *idx, int n,
+                         float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, s, u, n_points, idx, n, out);
+    hipLaunchKernelGGL(sample_kernel, dim3((n + 255) / 256), dim3(256), 0, s, u, n_points, pitch, nx, idx, n, out);
     return hipGetLastError();
 }
 

@@ -214,7 +214,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     const int z1 = min(z0 + a.dz, a.nz);
     const int zlo = max(z0 - R, 0);
     const int zhi = min(z1 + R, a.nz);
-    const int64_t plane = (int64_t)a.nx * a.ny;
+    const int64_t plane = (int64_t)a.pitch * a.ny;
     const uint32_t pbytes = (uint32_t)(plane * ES);  // one plane of a wavefield
     const uint32_t kbytes = (uint32_t)(plane * 4);   // one plane of kappa
     const uint32_t win = (uint32_t)(zhi - zlo) * pbytes;
@@ -235,8 +235,8 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
     for (int j = 0; j < RY; ++j) {
         const int y = yb + j;
         const bool in = xs < a.nx && y < a.ny;
-        coff[j] = in ? (uint32_t)(y * a.nx + xs) * (uint32_t)ES : kOOB;
-        koff[j] = in ? (uint32_t)(y * a.nx + xs) * 4u : kOOB;
+        coff[j] = in ? (uint32_t)(y * a.pitch + xs) * (uint32_t)ES : kOOB;
+        koff[j] = in ? (uint32_t)(y * a.pitch + xs) * 4u : kOOB;
     }
     uint32_t hg[NHI];
     int hl[NHI];
@@ -264,7 +264,7 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
         }
         hl[i] = valid ? lrow * LW + lcol : LROWS * LW;
         hg[i] = (valid && gxx >= 0 && gxx < a.nx && gyy >= 0 && gyy < a.ny)
-                    ? (uint32_t)(gyy * a.nx + gxx) * (uint32_t)ES : kOOB;
+                    ? (uint32_t)(gyy * a.pitch + gxx) * (uint32_t)ES : kOOB;
     }
 
     // ---- fused single source ------------------------------------------------
@@ -275,8 +275,8 @@ __device__ __forceinline__ void zmarch_body(const SweepArgs &a, int b)
         if (s >= 0 && s < plane * a.nz) {
             const int sz = (int)(s / plane);
             const int rem = (int)(s - (int64_t)sz * plane);
-            const int sy = rem / a.nx, sx = rem - (rem / a.nx) * a.nx;
-            if (sz >= z0 && sz < z1) {
+            const int sy = rem / a.pitch, sx = rem - (rem / a.pitch) * a.pitch;
+            if (sz >= z0 && sz < z1 && sx < a.nx) {
                 s_z = sz;
                 s_amp = a.src_amp[a.it] * a.scale;
                 const int dj = sy - yb, de = sx - xs;
@@ -441,8 +441,8 @@ __global__ void __launch_bounds__(1024) plain_kernel(SweepArgs a)
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z * blockDim.z + threadIdx.z;
     if (x >= a.nx || y >= a.ny || z >= a.nz) return;
-    const int64_t sy = a.nx;
-    const int64_t sz = (int64_t)a.nx * a.ny;
+    const int64_t sy = a.pitch;
+    const int64_t sz = (int64_t)a.pitch * a.ny;
     const int64_t p = (int64_t)z * sz + (int64_t)y * sy + x;
     const ST *u = (const ST *)a.ucur;
     const float u0 = (float)u[p];

@@ -72,7 +72,7 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     const int zs = z0 - R, ze = z1 + R;            // step-1 planes [zs, ze)
     const int zlo = max(z0 - 2 * R, 0);
     const int zhi = min(z1 + 2 * R, a.nz);
-    const int64_t plane = (int64_t)a.nx * a.ny;
+    const int64_t plane = (int64_t)a.pitch * a.ny;
     const uint32_t pbytes = (uint32_t)(plane * ES);
     const uint32_t kbytes = (uint32_t)(plane * 4);
     const uint32_t win = (uint32_t)(zhi - zlo) * pbytes;
@@ -89,8 +89,8 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     const int yy = ey0 + ty;
     const bool in = xs >= 0 && xs < a.nx && yy >= 0 && yy < a.ny;
     const bool own = tx >= HV && tx < BX - HV && ty >= R && ty < BY - R;
-    const uint32_t coff = in ? (uint32_t)(yy * a.nx + xs) * (uint32_t)ES : kOOB;
-    const uint32_t koff = in ? (uint32_t)(yy * a.nx + xs) * 4u : kOOB;
+    const uint32_t coff = in ? (uint32_t)(yy * a.pitch + xs) * (uint32_t)ES : kOOB;
+    const uint32_t koff = in ? (uint32_t)(yy * a.pitch + xs) * 4u : kOOB;
     const uint32_t soff = own ? coff : kOOB;  // stores: own points only
     const uint32_t skoff = own ? koff : kOOB;
 
@@ -120,7 +120,7 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
         }
         hl[i] = valid ? lrow * LW + lcol : LROWS * LW;
         hg[i] = (valid && gxx >= 0 && gxx < a.nx && gyy >= 0 && gyy < a.ny)
-                    ? (uint32_t)(gyy * a.nx + gxx) * (uint32_t)ES : kOOB;
+                    ? (uint32_t)(gyy * a.pitch + gxx) * (uint32_t)ES : kOOB;
     }
 
     // Single source at steps it (into u^{n+1}) and it+1 (into u^{n+2}).
@@ -131,8 +131,8 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
         if (s >= 0 && s < plane * a.nz) {
             const int sz = (int)(s / plane);
             const int rem = (int)(s - (int64_t)sz * plane);
-            const int sy = rem / a.nx, sx = rem - (rem / a.nx) * a.nx;
-            if (sz >= zs && sz < ze) {
+            const int sy = rem / a.pitch, sx = rem - (rem / a.pitch) * a.pitch;
+            if (sz >= zs && sz < ze && sx < a.nx) {
                 s_z = sz;
                 s_amp1 = a.src_amp[a.it] * a.scale;
                 s_amp2 = a.src_amp[a.it + 1] * a.scale;

@@ -255,6 +255,35 @@ def test_vector_width_follows_nx():
     p.stencil_destroy(ctx)
 
 
+def test_pitch_validation_and_vector_width():
+    # pitch >= nx; vector tiles need vw to divide nx and the pitch; sizes
+    # checked against the padded rows; 0 means nx.
+    with pytest.raises(p.StencilError) as e:
+        _init(nx=64, pitch=63)
+    assert e.value.status == p.EINVAL
+    with pytest.raises(p.StencilError) as e:
+        _init(nx=4096, ny=8192, nz=4, pitch=65536 + 4096)  # a plane of pitch * ny values over 2^29
+    assert e.value.status == p.EINVAL
+    for nx, pitch, vw in ((250, 256, 2), (200, 224, 4), (200, 226, 2), (61, 64, 1), (64, 0, 4)):
+        ctx = _init(nx=nx, ny=20, nz=12, pitch=pitch)
+        assert p.stencil_get_tile(ctx).vw == vw, (nx, pitch)
+        if vw < 4:
+            four = p.stencil_list_tiles(4, True)[0]
+            four.dz = 8
+            with pytest.raises(p.StencilError) as e:
+                p.stencil_set_tile(ctx, four)
+            assert e.value.status == p.EUNSUPPORTED
+        p.stencil_destroy(ctx)
+    # Field sizes follow the pitch: u_cur overlapping the padded u_prev is an alias.
+    ctx = _init(nx=250, ny=20, nz=12, pitch=256)
+    n = 256 * 20 * 12 * 4
+    base = 1 << 40
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_step(ctx, base, base + 2 * n, base + 2 * n + 250 * 20 * 12 * 4, 0, None, 0)
+    assert e.value.status == p.EALIAS
+    p.stencil_destroy(ctx)
+
+
 def test_eight_point_tiles_for_16bit_storage():
     # 16-bit storage has eight-point tiles (one 16-byte access per lane) for
     # nx % 8 == 0; FP32 storage has none.
@@ -454,21 +483,22 @@ def test_tune_cache_entries_at_init(tmp_path, monkeypatch):
     default = p.stencil_get_tile(ctx).as_dict()
     p.stencil_destroy(ctx)
     cache.write_text("garbage line\n" +
-                     _entry("R4 f32 64 48 41 2 32 8 1 16 4 1 0 1.0 1.0") +    # another grid
-                     _entry("R5 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0") +    # another radius
-                     _entry("R4 f16 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0") +    # another storage
-                     _entry("R4 f32 64 48 40 3 18 40 1 16 4 1 0 1.0 1.0"))    # a two-step entry
+                     _entry("R4 f32 64 48 41 64 2 32 8 1 16 4 1 0 1.0 1.0") +    # another grid
+                     _entry("R4 f32 64 48 40 128 2 32 8 1 16 4 1 0 1.0 1.0") +   # another row pitch
+                     _entry("R5 f32 64 48 40 64 2 32 8 1 16 4 1 0 1.0 1.0") +    # another radius
+                     _entry("R4 f16 64 48 40 64 2 32 8 1 16 4 1 0 1.0 1.0") +    # another storage
+                     _entry("R4 f32 64 48 40 64 3 18 40 1 16 4 1 0 1.0 1.0"))    # a two-step entry
     ctx = _init(nx=64, ny=48, nz=40)
     assert p.stencil_get_tile(ctx).as_dict() == default
     p.stencil_destroy(ctx)
     with open(cache, "a") as f:
-        f.write(_entry("R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0"))
+        f.write(_entry("R4 f32 64 48 40 64 2 32 8 1 16 4 1 0 1.0 1.0"))
     ctx = _init(nx=64, ny=48, nz=40)
     t = p.stencil_get_tile(ctx)
     assert (t.kind, t.bx, t.by, t.ry, t.dz, t.vw, t.pf) == (p.TILE_ZMARCH, 32, 8, 1, 16, 4, 0)
     p.stencil_destroy(ctx)
     with open(cache, "a") as f:
-        f.write(_entry("R4 f32 64 48 40 2 7 3 1 16 4 1 0 1.0 1.0"))  # no such kernel: default
+        f.write(_entry("R4 f32 64 48 40 64 2 7 3 1 16 4 1 0 1.0 1.0"))  # no such kernel: default
     ctx = _init(nx=64, ny=48, nz=40)
     assert p.stencil_get_tile(ctx).as_dict() == default
     p.stencil_destroy(ctx)
@@ -508,7 +538,7 @@ def test_tune_cache_ignores_entries_of_other_builds(tmp_path, monkeypatch):
     arch, hip, rt, src = bid.split("/")
     stale = [f"{arch}/{hip}/{rt}/src0123456789abcdef", f"{arch}/hip1/{rt}/{src}", f"{arch}/{hip}/rt1/{src}",
              f"gfx942/{hip}/{rt}/{src}"]
-    good = "R4 f32 64 48 40 2 32 8 1 16 4 1 0 1.0 1.0"
+    good = "R4 f32 64 48 40 64 2 32 8 1 16 4 1 0 1.0 1.0"
     cache.write_text("".join(_entry(good, b) for b in stale) + "gfx950 " + good + "\n")
     monkeypatch.setenv("STENCIL_TUNE_CACHE", str(cache))
     monkeypatch.delenv("STENCIL_LOG", raising=False)
