@@ -471,6 +471,53 @@ def paper_bench(args) -> int:
     return 0
 
 
+def pitch_bench(args) -> int:
+    """Rows padded to 128 bytes at the paper's per-process shapes (R = 5):
+    Gpt/s of a 448-step run with the searched tile for the grid as given,
+    the same grid with padded rows, and a grid of the padded width and the
+    same volume (the aligned reference)."""
+    import torch
+
+    import paper_1310_8232_amd as p
+    import workloads
+
+    iters = 448
+    dev = torch.device("cuda:0")
+    shapes = [(200, 200, 800), (300, 300, 800), (250, 250, 1500)]
+    if args.paper_shapes:
+        shapes = [tuple(int(v) for v in sh.split("x")) for sh in args.paper_shapes.split(",")]
+    out = {}
+
+    def run(nx, ny, nz, pitch):
+        c = workloads.config_layered(nx, ny, nz, nt=iters, radius=5)
+        prop = p.Propagator(torch.from_numpy(c["v"]).to(dev), c["h"], c["dt"], 5, vmax=c["vmax"], pitch=pitch)
+        idx = torch.tensor([prop.index(nz // 2, ny // 2, nx // 2)], dtype=torch.int64, device=dev)
+        amp = torch.from_numpy(c["amp"].reshape(-1, 1)).to(dev)
+        src = p.make_src(idx, amp)
+        rep, _, _ = prop.tune(n_iter=args.tune_iter, n_rep=3)
+        a, b = prop.zeros(), prop.zeros()
+        ms, _, _ = time_steps(prop, a, b, iters, 0, src, torch.cuda.current_stream())
+        r = {"grid": [nx, ny, nz], "pitch": prop.pitch, "tile": rep["tile"], "ms_448": round(ms, 3),
+             "gpts": round(nx * ny * nz * iters / (ms * 1e-3) / 1e9, 2)}
+        del prop, a, b
+        torch.cuda.empty_cache()
+        return r
+
+    for (nx, ny, nz) in shapes:
+        plain = run(nx, ny, nz, None)
+        padded = run(nx, ny, nz, "align")
+        P = padded["pitch"]
+        nz_ref = max(1, round(nx * nz / P))
+        ref = run(P, ny, nz_ref, None)
+        out[f"{nx}x{ny}x{nz}"] = {"as_given": plain, "padded": padded, "aligned_same_volume": ref,
+                                  "padded_vs_given": round(padded["gpts"] / plain["gpts"], 4),
+                                  "padded_vs_aligned": round(padded["gpts"] / ref["gpts"], 4)}
+        print(f"bench: pitch {nx}x{ny}x{nz}: {plain['gpts']} -> {padded['gpts']} Gpt/s padded to {P} "
+              f"(aligned {P}x{ny}x{nz_ref}: {ref['gpts']})", file=sys.stderr, flush=True)
+    print(json.dumps({"padded_rows": out, "radius": 5, "iterations": iters}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -491,9 +538,11 @@ def main(argv=None):
     ap.add_argument("--no-two-step", action="store_true", help="search one-step tiles only")
     ap.add_argument("--paper-repeats", type=int, default=10, help="searches per policy (paper workload; the paper reports 10 executions)")
     ap.add_argument("--paper-shapes", type=str, default="", help="e.g. 200x200x800,300x300x800")
-    ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision", "paper"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "gradient", "batch", "precision", "paper", "pitch"),
+                    default="sweep",
                     help="sweep: the autotuned step (default); gradient: misfit + adjoint gradient; "
-                         "batch: 16 uneven shots")
+                         "batch: 16 uneven shots; precision: 16-bit storage; paper: the search experiments; "
+                         "pitch: rows padded to 128 bytes at the paper's shapes")
     ap.add_argument("--nt", type=int, default=0, help="time steps of the gradient workload (default 500)")
     ap.add_argument("--checkpoint-every", type=int, default=50)
     ap.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
@@ -524,6 +573,8 @@ def main(argv=None):
         return precision_bench(args)
     if args.workload == "paper":
         return paper_bench(args)
+    if args.workload == "pitch":
+        return pitch_bench(args)
     n = args.n
     nt = args.warmup + args.steps
     t0 = time.perf_counter()

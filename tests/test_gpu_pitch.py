@@ -129,11 +129,14 @@ def test_padded_sources_receivers_two_step_and_search():
     p.stencil_sample(prop.ctx, got[0], rec_p, out_p)
     torch.cuda.synchronize()
     assert torch.equal(out_p[:3], out_u) and float(out_p[3]) == 0.0
-    # Two steps per launch on padded rows: the bits of one-step launches.
-    two = prop.run(prop.zeros(), prop.zeros(), nt, s_p, temporal=2)
+    # Two steps per launch on padded rows (they take one source, fused): the
+    # bits of one-step launches.
+    s_1, keep_1 = src_for(prop, [prop.index(*pts[0])])
+    one = prop.run(prop.zeros(), prop.zeros(), nt, s_1)
+    two = prop.run(prop.zeros(), prop.zeros(), nt, s_1, temporal=2)
     torch.cuda.synchronize()
-    for g, t in zip(got, two):
-        assert torch.equal(g, t)
+    for o, t in zip(one, two):
+        assert torch.equal(o, t)
     # The search runs on padded rows; its tile gives the same bits.
     rep, _, _ = prop.tune(n_iter=2, n_rep=1)
     again = prop.run(prop.zeros(), prop.zeros(), nt, s_p)
@@ -141,7 +144,7 @@ def test_padded_sources_receivers_two_step_and_search():
     log(f"  searched tile {rep['tile']}")
     for g, a in zip(got, again):
         assert torch.equal(g, a)
-    del keep_u, keep_p, z
+    del keep_u, keep_p, keep_1, z
 
 
 def test_padded_shot_in_a_batch():
