@@ -298,9 +298,27 @@ typedef struct {
  * and mixed devices. */
 stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * batch as stencil_batch_create, whose descriptor table (the only device
+ * memory a batch uses beyond the shots' own fields) is placed in a
+ * library-owned static device array of 64 KiB per GPU instead of a
+ * hipMalloc'd one. Calls no hipMalloc/hipFree (host bookkeeping only);
+ * uploads the table with hipMemcpy. Limits: the table takes 2 x 136 B per
+ * z-march shot plus 4 B, each kernel group rounded up to 256 B, so about 230
+ * shots fit; a larger batch is refused with EINVAL and a message
+ * (stencil_last_error(NULL)) before any device call. Every static batch on a
+ * GPU shares that GPU's array: creating one replaces the table of the
+ * previous one, whose later stencil_batch_step calls return EINVAL. The
+ * caller must not create a static batch while steps of an earlier static
+ * batch on that GPU may still run (such calls overlap and race). Steps,
+ * launches count and destroy are as for stencil_batch_create. */
+stencil_status stencil_batch_create_static(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out);
+
 /* One step of every shot of the batch on `stream`; capture-safe (no
  * allocation, no synchronisation). EINVAL if it < it0 or it reaches the
- * shortest source length. */
+ * shortest source length, or for a static batch whose table a later
+ * stencil_batch_create_static on the same GPU replaced. */
 stencil_status stencil_batch_step(stencil_batch *b, int64_t it, void *stream);
 
 /* The blocksize search of stencil_tune run on a whole batch: every candidate

@@ -105,6 +105,7 @@ _sig = {
     "stencil_gradient_terms": (_i32, [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp]),
     "stencil_misfit": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "stencil_batch_create": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
+    "stencil_batch_create_static": (_i32, [ctypes.POINTER(StencilShot), _i32, _i64, ctypes.POINTER(_vp)]),
     "stencil_batch_step": (_i32, [_vp, _i64, _vp]),
     "stencil_batch_tune": (_i32, [ctypes.POINTER(StencilShot), _i32, ctypes.POINTER(StencilTuneOpts),
                                   ctypes.POINTER(StencilTuneReport), _vp]),
@@ -300,6 +301,14 @@ def stencil_batch_create(shots, it0: int = 0):
     """shots: list of (ctx, kappa, u_a, u_b, StencilSrc or None). Returns a handle."""
     out = _vp()
     _check(_lib.stencil_batch_create(_shot_array(shots), len(shots), int(it0), ctypes.byref(out)))
+    return out.value
+
+
+def stencil_batch_create_static(shots, it0: int = 0):
+    """As stencil_batch_create, with the descriptor table in the library's
+    static per-GPU table (no device allocation). Returns a handle."""
+    out = _vp()
+    _check(_lib.stencil_batch_create_static(_shot_array(shots), len(shots), int(it0), ctypes.byref(out)))
     return out.value
 
 

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <initializer_list>
@@ -58,6 +59,8 @@ struct stencil_batch {
     int64_t nt_min = 0;     // smallest source length (steps must stay below it)
     void *dmem = nullptr;
     int device = 0;
+    bool in_static = false;    // table in the device's static table (no hipMalloc)
+    uint64_t generation = 0;   // static table contents this batch was built with
 };
 
 namespace {
@@ -1329,11 +1332,44 @@ stencil_status stencil_misfit(const void *traces, const void *observed, int64_t 
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;
 }
 
+// ---------------------------------------------------------------------------
+// Static batch table: device memory that stencil_batch_create_static uses for
+// the batch kernel's descriptor table instead of a hipMalloc'd one. Each GPU
+// holds its own copy of the array at its own address, which
+// hipGetSymbolAddress returns with that GPU current (the array's name in host
+// code is not a device address). Every static batch on a device shares the
+// array; a later stencil_batch_create_static on the device replaces the
+// contents, and batches built before it are refused from then on (their
+// generation no longer matches).
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticTableBytes = 64 * 1024;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticTableBytes];
+
 namespace {
 
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+uint64_t g_static_gen[kMaxDevices] = {};
+
+// Device address of this device's static table (the device must be current).
+hipError_t static_table(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_static_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_ptr[device] = p;
+    }
+    *ptr = g_static_ptr[device];
+    return hipSuccess;
+}
+
 // Builds a batch; tiles[i] (when tiles != NULL) replaces shot i's context tile.
+// in_static: the device table goes into the device's static table.
 stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_tile *tiles, int64_t it0,
-                           stencil_batch **out)
+                           stencil_batch **out, bool in_static = false)
 {
     if (!shots || !out || n < 1 || n > 4096) return STENCIL_EINVAL;
     stencil_batch *bt = new (std::nothrow) stencil_batch;
@@ -1448,14 +1484,30 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
         begins.push_back(beg);
         total += 2 * round256(t0.size() * sizeof(SweepArgs)) + round256(beg.size() * sizeof(int));
     }
+    if (in_static && total > kStaticTableBytes) {
+        delete bt;
+        return fail(nullptr, STENCIL_EINVAL,
+                    "the batch's descriptor table needs " + std::to_string(total) + " bytes; the static table holds " +
+                        std::to_string(kStaticTableBytes) + " (fewer shots, or stencil_batch_create)");
+    }
+    std::unique_lock<std::mutex> lock(g_static_mu, std::defer_lock);
     if (!bt->groups.empty()) {
         DeviceGuard guard(bt->device);
-        hipError_t he = guard.status != hipSuccess ? guard.status : hipMalloc(&bt->dmem, total);
+        hipError_t he = guard.status;
+        char *p = nullptr;
+        if (he == hipSuccess && in_static) {
+            lock.lock();
+            void *base = nullptr;
+            he = static_table(bt->device, &base);
+            p = (char *)base;
+        } else if (he == hipSuccess) {
+            he = hipMalloc(&bt->dmem, total);
+            p = (char *)bt->dmem;
+        }
         if (he != hipSuccess) {
             delete bt;
-            return hip_fail(nullptr, he, "batch table allocation");
+            return hip_fail(nullptr, he, in_static ? "static batch table address" : "batch table allocation");
         }
-        char *p = (char *)bt->dmem;
         for (size_t gi = 0; gi < bt->groups.size(); ++gi) {
             auto &g = bt->groups[gi];
             for (int par = 0; par < 2; ++par) {
@@ -1463,7 +1515,7 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
                 size_t sz = tabs[par][gi].size() * sizeof(SweepArgs);
                 hipError_t he = hipMemcpy(p, tabs[par][gi].data(), sz, hipMemcpyHostToDevice);
                 if (he != hipSuccess) {
-                    hipFree(bt->dmem);
+                    if (bt->dmem) hipFree(bt->dmem);
                     delete bt;
                     return hip_fail(nullptr, he, "batch table upload");
                 }
@@ -1473,12 +1525,24 @@ stencil_status build_batch(const stencil_shot *shots, int32_t n, const stencil_t
             size_t sz = begins[gi].size() * sizeof(int);
             hipError_t he = hipMemcpy(p, begins[gi].data(), sz, hipMemcpyHostToDevice);
             if (he != hipSuccess) {
-                hipFree(bt->dmem);
+                if (bt->dmem) hipFree(bt->dmem);
                 delete bt;
                 return hip_fail(nullptr, he, "batch table upload");
             }
             p += round256(sz);
         }
+    }
+    if (in_static) {
+        // A batch without z-march groups does not touch the table, but it
+        // still replaces the contents' owner, so that the rule "the latest
+        // static batch on a device is the one that runs" has no exception.
+        if (!lock.owns_lock()) lock.lock();
+        if (bt->device < 0 || bt->device >= kMaxDevices) {
+            delete bt;
+            return fail(nullptr, STENCIL_EINVAL, "device number outside 0..63");
+        }
+        bt->in_static = true;
+        bt->generation = ++g_static_gen[bt->device];
     }
     *out = bt;
     return STENCIL_OK;
@@ -1491,10 +1555,21 @@ stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_
     return build_batch(shots, n, nullptr, it0, out);
 }
 
+stencil_status stencil_batch_create_static(const stencil_shot *shots, int32_t n, int64_t it0, stencil_batch **out)
+{
+    return build_batch(shots, n, nullptr, it0, out, true);
+}
+
 stencil_status stencil_batch_step(stencil_batch *bt, int64_t it, void *stream)
 {
     if (!bt) return STENCIL_EINVAL;
     if (it < bt->it0 || it >= bt->nt_min) return STENCIL_EINVAL;
+    if (bt->in_static) {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static_gen[bt->device] != bt->generation)
+            return fail(nullptr, STENCIL_EINVAL,
+                        "a later stencil_batch_create_static on this device replaced this batch's static table");
+    }
     const int par = (int)((it - bt->it0) & 1);
     DeviceGuard guard(bt->device);
     if (guard.status != hipSuccess) return STENCIL_EDEVICE;

@@ -449,6 +449,27 @@ def test_batch_rejects_buffers_shared_between_shots():
         p.stencil_destroy(c)
 
 
+def test_static_batch_table_limit():
+    # The static-table batch refuses a descriptor table larger than its
+    # 64 KiB array before any device call (fake pointers); a batch of plain
+    # tiles needs no table and is created on the CPU.
+    n_shots = 300
+    ctxs = [_init(nx=8, ny=8, nz=8) for _ in range(n_shots)]
+    assert p.stencil_get_tile(ctxs[0]).kind == p.TILE_ZMARCH
+    fb = 8 ** 3 * 4
+    base = 1 << 40
+    shots = [(c, base + 3 * i * fb, base + (3 * i + 1) * fb, base + (3 * i + 2) * fb, None)
+             for i, c in enumerate(ctxs)]
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_batch_create_static(shots)
+    assert e.value.status == p.EINVAL and "static table holds 65536" in str(e.value)
+    for c in ctxs[:2]:
+        p.stencil_set_tile(c, p.make_tile(p.TILE_PLAIN, bx=64, by=4, dz=1))
+    p.stencil_batch_destroy(p.stencil_batch_create_static(shots[:2]))
+    for c in ctxs:
+        p.stencil_destroy(c)
+
+
 @pytest.mark.parametrize("policy", ["worst", "min", "avg", "ob"])
 def test_select_skips_failed_candidates(policy):
     # A candidate whose launch failed is timed as +inf. As long as every
