@@ -686,7 +686,15 @@ def main(argv=None):
                    "timed_segments": seg, "stream_ceiling": ceiling},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     # what the figures above are per: one launch of the dominant kernel
+                     "kernel": "two-step sweep (zmarch2)" if temporal == 2 else "one-step sweep (zmarch)",
+                     "updates_per_launch": temporal, "algorithmic_bytes_per_launch": launch_bytes,
+                     "launch_ms": round(launch_ms, 5),
+                     # measured bytes per launch over the launch time: the rate the kernel moves
+                     "traffic_gbs": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 1),
+                     # the one-step sweep's 16 B per update at this update rate
+                     "one_step_equivalent_gbs": round(gpts * BYTES_PER_UPDATE, 1)},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -23,9 +23,15 @@ namespace p1310 {
 // Both LDS planes are double buffered and staged before the iteration's one
 // barrier. A chunk [z0, z1) of output planes runs step 1 over planes
 // z0-R .. z1+R-1 and one more iteration for the last step-2 plane. PF = 1
-// loads u^{n-1} and kappa one plane ahead; kappa for step 2 (own points) is
-// always loaded one plane ahead. Every point uses the canonical operation
-// order, so the results are the bits of two one-step sweeps. HBM traffic:
+// loads u^{n-1} and kappa one plane ahead. kappa for step 2 is not loaded
+// again: each lane keeps the kappa its step 1 loaded for the last R + 1
+// planes in a register queue, and step 2's plane z' = z - R - 1 is the oldest
+// of them. u^{n-1} and kappa are read over all of E, so the ring positions
+// are read by neighbouring workgroups too: those loads use the default
+// (cached) policy. The stencil sums run one radius at a time (the y pair of
+// radius m read from LDS and consumed before radius m + 1), which keeps the
+// register peak low; the per-point operation order is the canonical one, so
+// the results are the bits of two one-step sweeps. Algorithmic HBM traffic:
 // 20 B per point for two updates.
 // ---------------------------------------------------------------------------
 template <int R, int BX, int BY, int VW, int PF, typename ST>
@@ -92,7 +98,6 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     const uint32_t coff = in ? (uint32_t)(yy * a.pitch + xs) * (uint32_t)ES : kOOB;
     const uint32_t koff = in ? (uint32_t)(yy * a.pitch + xs) * 4u : kOOB;
     const uint32_t soff = own ? coff : kOOB;  // stores: own points only
-    const uint32_t skoff = own ? koff : kOOB;
 
     uint32_t hg[NHI];
     int hl[NHI];
@@ -145,7 +150,8 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     V q1[Q], q2[Q];
     V hh[2][NHI];
     V upf[2], kpf[2];  // PF: u^{n-1} and kappa of planes z (slot z & 1) and z + 1
-    V k2[2];           // kappa at own points of step-2 planes z' and z' + 1
+    constexpr int KQ = R + 1;
+    V kq2[KQ];         // kappa of the last R + 1 step-1 planes: plane p in slot (p - zs) mod (R + 1)
 
     auto plane_ok = [&](int p) { return p >= 0 && p < a.nz; };
     auto load_center = [&](V &dst, int p) {
@@ -164,7 +170,7 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     };
     auto load_pk = [&](V &u, V &k, int p) {
         if (plane_ok(p)) {
-            u = uload<ST, VW, kNT>(rp, coff, (uint32_t)(p - zlo) * pbytes);
+            u = uload<ST, VW, 0>(rp, coff, (uint32_t)(p - zlo) * pbytes);
             k = bload<VW, 0>(rk, koff, (uint32_t)(p - zlo) * kbytes);
         } else {
             u = vzero<VW>();
@@ -179,7 +185,8 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     for (int k = 0; k < Q; ++k) q2[k] = vzero<VW>();
     load_halo(hh[0], zs);
     if (PF) load_pk(upf[0], kpf[0], zs);
-    k2[0] = k2[1] = vzero<VW>();
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) kq2[k] = vzero<VW>();
 
     // Iteration z = zb + j keeps plane p of u^n and of u^{n+1} in queue slot
     // (p - zs + R) mod Q: plane z in slot (j + R) mod Q, plane z' = z - R - 1
@@ -221,8 +228,6 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
                 load_halo(hh[(j + 1) & 1], z + 1);
                 if (PF) load_pk(upf[(j + 1) & 1], kpf[(j + 1) & 1], z + 1);
             }
-            if (zq + 1 >= z0 && zq + 1 < z1)
-                k2[(j + 1) & 1] = bload<VW, 0>(rk, skoff, (uint32_t)(zq + 1 - zlo) * kbytes);
 
             // Step 2: u^{n+2}(z') on the own tile. Every lane runs it in every
             // iteration (no divergent branch, so the compiler schedules it
@@ -232,12 +237,6 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
             // the window for them).
             {
                 const int tyc = min(max(ty, R), BY - R - 1), txc = min(max(tx, HV), BX - HV - 1);
-                V yv[2 * R];
-#pragma unroll
-                for (int d = 0; d < R; ++d) {
-                    yv[d] = *reinterpret_cast<const V *>(buf2 + (tyc - R + d) * EX + txc * VW);
-                    yv[R + d] = *reinterpret_cast<const V *>(buf2 + (tyc + 1 + d) * EX + txc * VW);
-                }
                 const float *row = buf2 + tyc * EX + txc * VW - HX;
                 V xl[HV], xr[HV];
 #pragma unroll
@@ -246,27 +245,33 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
                     xr[v] = *reinterpret_cast<const V *>(row + HX + VW + v * VW);
                 }
                 const V &c1 = q2[sq];  // u^{n+1}(z')
-                const V &kq = k2[j & 1];
-                V out;
+                const V kq = kq2[j % KQ];  // kappa(z'), loaded by step 1 R + 1 iterations ago
+                float acc[VW];
 #pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    const float u0 = c1.a[e];
-                    float acc = a.c[0] * u0;
+                for (int e = 0; e < VW; ++e) acc[e] = a.c[0] * c1.a[e];
+                // One radius at a time: its y pair is read from LDS and used
+                // before the next radius's, so the taps of one radius are live
+                // at a time (the per-point operation order is unchanged).
 #pragma unroll
-                    for (int m = 1; m <= R; ++m) {
+                for (int m = 1; m <= R; ++m) {
+                    const V yp = *reinterpret_cast<const V *>(buf2 + (tyc + m) * EX + txc * VW);
+                    const V ym = *reinterpret_cast<const V *>(buf2 + (tyc - m) * EX + txc * VW);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
                         const int wp = HX + e + m, wm = HX + e - m;
                         const float xp = (wp < HX + VW) ? c1.a[wp - HX]
                                                         : xr[(wp - HX - VW) / VW].a[(wp - HX - VW) % VW];
                         const float xm = (wm >= HX) ? c1.a[wm - HX] : xl[wm / VW].a[wm % VW];
-                        const float yp = yv[R + m - 1].a[e];
-                        const float ym = yv[R - m].a[e];
                         const float zp = q2[(j + Q - 1 + m) % Q].a[e];
                         const float zm = q2[(j + Q - 1 - m) % Q].a[e];
-                        const float s = ((xp + xm) + (yp + ym)) + (zp + zm);
-                        acc = __builtin_fmaf(a.c[m], s, acc);
+                        const float s = ((xp + xm) + (yp.a[e] + ym.a[e])) + (zp + zm);
+                        acc[e] = __builtin_fmaf(a.c[m], s, acc[e]);
                     }
-                    out.a[e] = __builtin_fmaf(kq.a[e], acc, __builtin_fmaf(2.0f, u0, -un.a[e]));
                 }
+                V out;
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    out.a[e] = __builtin_fmaf(kq.a[e], acc[e], __builtin_fmaf(2.0f, c1.a[e], -un.a[e]));
                 if (zq == s_z) {
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
@@ -277,12 +282,6 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
 
             // Step 1: u^{n+1}(z) on E.
             if (st1) {
-                V yv[2 * R];
-#pragma unroll
-                for (int d = 0; d < R; ++d) {
-                    yv[d] = *reinterpret_cast<const V *>(buf1 + (ty + d) * LW + HX + tx * VW);
-                    yv[R + d] = *reinterpret_cast<const V *>(buf1 + (R + ty + 1 + d) * LW + HX + tx * VW);
-                }
                 const float *row = buf1 + (R + ty) * LW + tx * VW;
                 V xl[HV], xr[HV];
 #pragma unroll
@@ -290,32 +289,36 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
                     xl[v] = *reinterpret_cast<const V *>(row + v * VW);
                     xr[v] = *reinterpret_cast<const V *>(row + HX + VW + v * VW);
                 }
-                V out;
+                float acc[VW];
 #pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    const float u0 = q1[sc].a[e];
-                    float acc = a.c[0] * u0;
+                for (int e = 0; e < VW; ++e) acc[e] = a.c[0] * q1[sc].a[e];
 #pragma unroll
-                    for (int m = 1; m <= R; ++m) {
+                for (int m = 1; m <= R; ++m) {
+                    const V yp = *reinterpret_cast<const V *>(buf1 + (R + ty + m) * LW + HX + tx * VW);
+                    const V ym = *reinterpret_cast<const V *>(buf1 + (R + ty - m) * LW + HX + tx * VW);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
                         const int wp = HX + e + m, wm = HX + e - m;
                         const float xp = (wp < HX + VW) ? q1[sc].a[wp - HX]
                                                         : xr[(wp - HX - VW) / VW].a[(wp - HX - VW) % VW];
                         const float xm = (wm >= HX) ? q1[sc].a[wm - HX] : xl[wm / VW].a[wm % VW];
-                        const float yp = yv[R + m - 1].a[e];
-                        const float ym = yv[R - m].a[e];
                         const float zp = q1[(j + R + m) % Q].a[e];
                         const float zm = q1[(j + R - m + Q) % Q].a[e];
-                        const float s = ((xp + xm) + (yp + ym)) + (zp + zm);
-                        acc = __builtin_fmaf(a.c[m], s, acc);
+                        const float s = ((xp + xm) + (yp.a[e] + ym.a[e])) + (zp + zm);
+                        acc[e] = __builtin_fmaf(a.c[m], s, acc[e]);
                     }
-                    out.a[e] = __builtin_fmaf(kp.a[e], acc, __builtin_fmaf(2.0f, u0, -up.a[e]));
                 }
+                V out;
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    out.a[e] = __builtin_fmaf(kp.a[e], acc[e], __builtin_fmaf(2.0f, q1[sc].a[e], -up.a[e]));
                 if (z == s_z) {
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
                         if (e == s_e) out.a[e] = __builtin_fmaf(kp.a[e], s_amp1, out.a[e]);
                 }
                 q2[sc] = out;
+                kq2[j % KQ] = kp;
                 if (z >= z0 && z < z1) ustore<ST, VW, kNT>(out, rn1, soff, (uint32_t)(z - zlo) * pbytes);
             }
         }

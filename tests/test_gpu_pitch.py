@@ -166,3 +166,62 @@ def test_padded_shot_in_a_batch():
         a, b = pr.run(pr.zeros(), pr.zeros(), nt, s)
         torch.cuda.synchronize()
         assert torch.equal(a, bn) and torch.equal(b, bnm1)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_padded_rows_16bit_storage(storage):
+    # 16-bit wavefields with rows padded to 128 bytes (64 values): grid bits
+    # equal the unpadded run's for the default tile and every 16-bit tile.
+    nx, ny, nz = 200, 30, 26
+    v, dt, vmax, u0, um1 = _case(nx, ny, nz, seed=800)
+    nt = 5
+    log(f"case: {storage} storage, {nx}x{ny}x{nz}, rows padded to 128 bytes")
+
+    def run(pitch, tile):
+        prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax, storage=storage, storage_scale=256.0, pitch=pitch,
+                            tile=tile)
+        P = prop.pitch
+        a = prop.to_storage(cuda(_padded(u0, P, 0.0) if P != nx else u0))
+        b = prop.to_storage(cuda(_padded(um1, P, 0.0) if P != nx else um1))
+        a, b = prop.run(a, b, nt)
+        torch.cuda.synchronize()
+        return prop.grid(a).cpu(), prop.grid(b).cpu(), P
+
+    ref = run(None, None)
+    assert run("align", None)[2] == 256
+    tiles = [None] + [p.make_tile(p.TILE_ZMARCH, t.bx, t.by, t.ry, 8, t.vw, 1, t.pf)
+                      for w in (1, 8) for t in p.stencil_list_tiles(4, w, storage)]
+    for t in tiles:
+        got = run("align", t)
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1]), f"tile {t}"
+
+
+def test_padded_rows_one_point_two_step_and_gradient():
+    # nx = 61 with rows of 64: one-point vectors; the one-point two-step tile
+    # gives the one-step bits; the misfit gradient on padded fields equals the
+    # unpadded gradient at every grid point (padding stays 0).
+    from paper_1310_8232_amd import adjoint
+    nx, ny, nz, nt = 61, 29, 23, 30
+    c = workloads.config_gradient(nx, ny, nz, nt=nt)
+    log("case: 61x29x23 rows of 64: one-point two-step tile, misfit gradient")
+    out = {}
+    for pitch in (None, 64):
+        prop = p.Propagator(cuda(c["m_cur"]), c["h"], c["dt"], 4, slowness2=True, pitch=pitch)
+        src_idx = [prop.index(*np.unravel_index(int(s), (nz, ny, nx))) for s in c["src_idx"]]
+        rec_idx = [prop.index(*np.unravel_index(int(r), (nz, ny, nx))) for r in c["rec_idx"]]
+        survey = adjoint.Survey(cuda(np.array(src_idx, np.int64), torch.int64), cuda(c["amp"].reshape(-1, 1)),
+                                cuda(np.array(rec_idx, np.int64), torch.int64))
+        s = survey.src()
+        one = prop.run(prop.zeros(), prop.zeros(), nt, s)
+        prop.tile = p.make_tile(p.TILE_ZMARCH2, 32, 16, 1, 8, 1, 1, 0)
+        two = prop.run(prop.zeros(), prop.zeros(), nt, s, temporal=2)
+        torch.cuda.synchronize()
+        for o, t in zip(one, two):
+            assert torch.equal(o, t), f"pitch {pitch}"
+        obs = torch.zeros((nt, len(rec_idx)), device="cuda:0")
+        J, g, tr = adjoint.misfit_gradient(prop, survey, obs, checkpoint_every=7)
+        torch.cuda.synchronize()
+        out[pitch] = (J.item(), prop.grid(g).cpu(), tr.cpu(), g.cpu())
+    assert out[None][0] == out[64][0]
+    assert torch.equal(out[None][1], out[64][1]) and torch.equal(out[None][2], out[64][2])
+    assert torch.count_nonzero(out[64][3][..., nx:]) == 0
