@@ -270,7 +270,8 @@ stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *c
 
 /* resid[i] = traces[i] - observed[i] (FP32, i < count; resid may be NULL) and
  * *misfit = 1/2 sum resid^2 accumulated in FP64 in a fixed order (device
- * double). All pointers are device memory. */
+ * double). All pointers are device memory; with count = 0 traces and
+ * observed may be NULL and *misfit is set to 0. */
 stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
                               void *stream);
 

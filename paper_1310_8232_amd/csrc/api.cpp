@@ -1326,7 +1326,8 @@ stencil_status stencil_gradient_terms(stencil_ctx *ctx, int32_t m, const void *c
 stencil_status stencil_misfit(const void *traces, const void *observed, int64_t count, void *resid, double *misfit,
                               void *stream)
 {
-    if (!traces || !observed || !misfit || count < 0) return STENCIL_EINVAL;
+    if (!misfit || count < 0) return STENCIL_EINVAL;
+    if (count > 0 && (!traces || !observed)) return STENCIL_EINVAL;  // count 0: J = 0, no sample is read
     hipError_t e = p1310::launch_misfit((const float *)traces, (const float *)observed, count, (float *)resid, misfit,
                                         (hipStream_t)stream);
     return e == hipSuccess ? STENCIL_OK : STENCIL_EDEVICE;

@@ -490,3 +490,30 @@ def test_two_streams_concurrently():
     torch.cuda.synchronize()
     for (_, _, _, ref), got in zip(cases, outs):
         assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])
+
+
+def test_empty_inputs():
+    # Zero steps leave the fields as they are (one- and two-step loops); a
+    # source list of n = 0, zero receivers, an empty misfit (J = 0) and the
+    # gradient terms over no steps are no-ops, not errors.
+    nx, ny, nz = 40, 24, 16
+    v, dt, vmax, u0, um1 = _random_case(nx, ny, nz, seed=31)
+    prop = p.Propagator(cuda(v), 10.0, dt, 4, vmax=vmax)
+    a, b = cuda(u0), cuda(um1)
+    for temporal in (1, 2):
+        x, y = prop.run(a, b, 0, None, temporal=temporal)
+        torch.cuda.synchronize()
+        assert x is a and y is b and np.array_equal(a.cpu().numpy(), u0) and np.array_equal(b.cpu().numpy(), um1)
+    empty_src = p.make_src(torch.zeros(0, dtype=torch.int64, device="cuda:0"),
+                           torch.zeros((5, 0), dtype=torch.float32, device="cuda:0"))
+    ref = gpu_run(v, 10.0, dt, vmax, 4, 3, u0, um1)[:2]
+    x, y = prop.run(cuda(u0), cuda(um1), 3, empty_src)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), ref[0]) and np.array_equal(y.cpu().numpy(), ref[1])
+    out = torch.full((1,), 5.0, device="cuda:0")
+    p.stencil_sample(prop.ctx, x, torch.zeros(0, dtype=torch.int64, device="cuda:0"), out)
+    J = torch.full((), 7.0, dtype=torch.float64, device="cuda:0")
+    e = torch.zeros(0, device="cuda:0")
+    p.stencil_misfit(e, e, None, J)
+    torch.cuda.synchronize()
+    assert float(out[0]) == 5.0 and float(J) == 0.0
