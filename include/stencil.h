@@ -305,9 +305,9 @@ stencil_status stencil_batch_create(const stencil_shot *shots, int32_t n, int64_
  * memory a batch uses beyond the shots' own fields) is placed in a
  * library-owned static device array of 64 KiB per GPU instead of a
  * hipMalloc'd one. Calls no hipMalloc/hipFree (host bookkeeping only);
- * uploads the table with hipMemcpy. Limits: the table takes 2 x 136 B per
- * z-march shot plus 4 B, each kernel group rounded up to 256 B, so about 230
- * shots fit; a larger batch is refused with EINVAL and a message
+ * uploads the table with hipMemcpy. Limits: the table takes 2 x 144 B per
+ * z-march shot plus 4 B, each of a kernel group's three parts rounded up to
+ * 256 B, so 224 shots of one tile shape fit; a larger batch is refused with EINVAL and a message
  * (stencil_last_error(NULL)) before any device call. Every static batch on a
  * GPU shares that GPU's array: creating one replaces the table of the
  * previous one, whose later stencil_batch_step calls return EINVAL. The

@@ -470,6 +470,28 @@ def test_static_batch_table_limit():
         p.stencil_destroy(c)
 
 
+def test_static_batch_table_boundary():
+    # 224 z-march shots of one tile shape fill the 64 KiB table exactly
+    # (two parity tables of 224 x 144 B and 224 first-workgroup ints, each
+    # rounded up to 256 B); 225 are refused before any device call. Without
+    # a GPU the 224-shot batch passes the size check and then fails at the
+    # table's device address instead.
+    ctxs = [_init(nx=8, ny=8, nz=8) for _ in range(225)]
+    fb = 8 ** 3 * 4
+    base = 1 << 40
+    shots = [(c, base + 3 * i * fb, base + (3 * i + 1) * fb, base + (3 * i + 2) * fb, None)
+             for i, c in enumerate(ctxs)]
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_batch_create_static(shots)
+    assert e.value.status == p.EINVAL and "needs 66048 bytes" in str(e.value)
+    try:
+        p.stencil_batch_destroy(p.stencil_batch_create_static(shots[:224]))
+    except p.StencilError as err:
+        assert "static table holds" not in str(err), str(err)
+    for c in ctxs:
+        p.stencil_destroy(c)
+
+
 @pytest.mark.parametrize("policy", ["worst", "min", "avg", "ob"])
 def test_select_skips_failed_candidates(policy):
     # A candidate whose launch failed is timed as +inf. As long as every
