@@ -154,28 +154,23 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     V kq2[KQ];         // kappa of the last R + 1 step-1 planes: plane p in slot (p - zs) mod (R + 1)
 
     auto plane_ok = [&](int p) { return p >= 0 && p < a.nz; };
+    // A plane outside the grid is read through an out-of-range vector offset
+    // (and a zero scalar offset), which returns zeros: the loads need no
+    // branch and no zeroing moves.
     auto load_center = [&](V &dst, int p) {
-        if (plane_ok(p)) dst = uload<ST, VW, 0>(rc, coff, (uint32_t)(p - zlo) * pbytes);
-        else dst = vzero<VW>();
+        const bool ok = plane_ok(p);
+        dst = uload<ST, VW, 0>(rc, ok ? coff : kOOB, ok ? (uint32_t)(p - zlo) * pbytes : 0u);
     };
     auto load_halo = [&](V (&dst)[NHI], int p) {
-        if (plane_ok(p)) {
-            const uint32_t so = (uint32_t)(p - zlo) * pbytes;
+        const bool ok = plane_ok(p);
+        const uint32_t so = ok ? (uint32_t)(p - zlo) * pbytes : 0u;
 #pragma unroll
-            for (int i = 0; i < NHI; ++i) dst[i] = uload<ST, VW, 0>(rc, hg[i], so);
-        } else {
-#pragma unroll
-            for (int i = 0; i < NHI; ++i) dst[i] = vzero<VW>();
-        }
+        for (int i = 0; i < NHI; ++i) dst[i] = uload<ST, VW, 0>(rc, ok ? hg[i] : kOOB, so);
     };
     auto load_pk = [&](V &u, V &k, int p) {
-        if (plane_ok(p)) {
-            u = uload<ST, VW, 0>(rp, coff, (uint32_t)(p - zlo) * pbytes);
-            k = bload<VW, 0>(rk, koff, (uint32_t)(p - zlo) * kbytes);
-        } else {
-            u = vzero<VW>();
-            k = vzero<VW>();
-        }
+        const bool ok = plane_ok(p);
+        u = uload<ST, VW, 0>(rp, ok ? coff : kOOB, ok ? (uint32_t)(p - zlo) * pbytes : 0u);
+        k = bload<VW, 0>(rk, ok ? koff : kOOB, ok ? (uint32_t)(p - zlo) * kbytes : 0u);
     };
 
     // Prologue: u^n planes zs-R .. zs+R (queue slots 0..2R), halo of plane zs.
