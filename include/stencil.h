@@ -97,7 +97,11 @@ typedef struct {
     int32_t vw;     /* x points per thread: 8 (ZMARCH, 16-bit storage), 4, 2 (ZMARCH, FP32
                        storage) or 1; must divide nx and the pitch; 0 = the widest that does */
     int32_t xcd;    /* 1 = XCD-aware workgroup order (neighbour tiles share an L2) */
-    int32_t pf;     /* 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2) */
+    int32_t pf;     /* bit 0: 1 = prefetch u^{n-1} and kappa one plane ahead (ZMARCH, ZMARCH2).
+                       ZMARCH2 only, bits 1-3: edge pacing code p in 0..7: with at least
+                       three tile columns, the workgroups of the first and last column
+                       pause about 4p x 64 cycles per plane (0 = off), so that they keep
+                       step with their neighbours (see stencil_step2) */
 } stencil_tile;
 
 typedef struct {
@@ -202,7 +206,13 @@ stencil_status stencil_step_to(stencil_ctx *ctx, const void *kappa, const void *
  * At most one source (EUNSUPPORTED otherwise; a negative count is EINVAL);
  * it+1 < src->nt (EINVAL).
  * Results are bit-identical to two stencil_step calls. Uses the context's
- * two-step tile; FP32 storage. Capture-safe. */
+ * two-step tile; FP32 storage. Capture-safe. Edge pacing (tile.pf bits 1-3):
+ * the tiles of the grid's first and last tile column have out-of-grid halo
+ * columns, which cost no memory traffic, so they march ahead of their
+ * neighbours, and the halo lines the two share are then fetched twice
+ * instead of being found in the L2; a short pause per plane in those tiles
+ * keeps them in step. It changes timing only, never results; the search
+ * (stencil_tune with temporal = 2) times paced and unpaced tiles. */
 stencil_status stencil_step2(stencil_ctx *ctx, const void *kappa, const void *u_cur, const void *u_prev,
                              void *u_next, void *u_next2, int64_t it, const stencil_src *src, void *stream);
 

@@ -165,8 +165,11 @@ std::string tile_text(const stencil_tile &t)
 {
     char b[160];
     static const char *kind[] = {"auto", "plain", "zmarch", "zmarch2"};
-    std::snprintf(b, sizeof b, "%s %dx%d ry%d dz%d vw%d xcd%d pf%d", (t.kind >= 0 && t.kind <= 3) ? kind[t.kind] : "?",
-                  t.bx, t.by, t.ry, t.dz, t.vw, t.xcd, t.pf);
+    const int n = std::snprintf(b, sizeof b, "%s %dx%d ry%d dz%d vw%d xcd%d pf%d",
+                                (t.kind >= 0 && t.kind <= 3) ? kind[t.kind] : "?", t.bx, t.by, t.ry, t.dz, t.vw, t.xcd,
+                                t.kind == STENCIL_TILE_ZMARCH2 ? (t.pf & 1) : t.pf);
+    if (t.kind == STENCIL_TILE_ZMARCH2 && (t.pf >> 1) && n > 0 && n < (int)sizeof b)
+        std::snprintf(b + n, sizeof b - n, " pace%d", t.pf >> 1);
     return b;
 }
 
@@ -233,7 +236,7 @@ const Z2Variant *find_variant2(const stencil_ctx *ctx, const stencil_tile &t)
     for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
         const Z2Variant *v = p1310::zmarch2_variant(i);
         if (v->R == ctx->R && v->st == ctx->st && v->bx == t.bx && v->by == t.by && v->vw == t.vw &&
-            v->pf == t.pf)
+            v->pf == (t.pf & 1))
             return v;
     }
     return nullptr;
@@ -261,6 +264,8 @@ stencil_status check_tile(stencil_ctx *ctx, const stencil_tile &in, stencil_tile
     if (t.kind == STENCIL_TILE_ZMARCH2) {
         if (t.vw == 0) t.vw = vec4_ok(ctx) ? 4 : 1;
         if (t.vw < 1 || !vw_fits(ctx, t.vw)) return fail(ctx, STENCIL_EUNSUPPORTED, "vw must divide nx and the pitch");
+        if (t.pf < 0 || t.pf > 15)
+            return fail(ctx, STENCIL_EUNSUPPORTED, "two-step pf: bit 0 prefetch, bits 1-3 edge pacing (0..15)");
         t.ry = 1;
         const Z2Variant *v = find_variant2(ctx, t);
         if (!v) return fail(ctx, STENCIL_EUNSUPPORTED, "no compiled two-step kernel for this (bx, by, vw), radius, storage");
@@ -578,6 +583,13 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
                 for (int xcd = 1; xcd >= 0; --xcd) {
                     stencil_tile t = {STENCIL_TILE_ZMARCH2, v->bx, v->by, 1, (int32_t)dz, v->vw, xcd, v->pf};
                     push_unique(ctx, out, t);
+                    // Edge pacing, with the XCD order that lets neighbours
+                    // share an L2 (the pause that keeps the edge tiles in
+                    // step depends on the plane time: three lengths).
+                    for (int pace = 4; xcd && pace <= 6; ++pace) {
+                        t.pf = v->pf | (pace << 1);
+                        push_unique(ctx, out, t);
+                    }
                 }
             }
         }
@@ -708,6 +720,7 @@ hipError_t enqueue_step2(const stencil_ctx *ctx, const stencil_tile &t, const fl
     a.gy = (int)((d.ny + v->own_y - 1) / v->own_y);
     a.gz = (int)((d.nz + t.dz - 1) / t.dz);
     a.xcd = t.xcd;
+    a.pace = (t.pf >> 1) & 7;
     return p1310::launch_zmarch2(*v, a, s);
 }
 

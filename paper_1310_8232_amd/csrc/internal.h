@@ -28,6 +28,7 @@ struct SweepArgs {
     int nsrc;
     int64_t it;
     float scale;             // storage scale: source amplitudes are multiplied by it
+    int pace;                // two-step kernels: edge pacing code 0..7 (0 = off)
 };
 
 // Wavefield storage types (stencil_storage).

@@ -32,7 +32,11 @@ namespace p1310 {
 // radius m read from LDS and consumed before radius m + 1), which keeps the
 // register peak low; the per-point operation order is the canonical one, so
 // the results are the bits of two one-step sweeps. Algorithmic HBM traffic:
-// 20 B per point for two updates.
+// 20 B per point for two updates. Edge pacing (SweepArgs::pace): with the XCD
+// order, the tiles of one XCD share the halo lines of their neighbours in its
+// L2 only while they march near the same plane; the first and last tile
+// columns read fewer bytes and would run ahead, so they pause for a fixed
+// time per plane (a timing option only: the arithmetic is untouched).
 // ---------------------------------------------------------------------------
 template <int R, int BX, int BY, int VW, int PF, typename ST>
 __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
@@ -76,6 +80,9 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
     const int z0 = zc * a.dz;
     const int z1 = min(z0 + a.dz, a.nz);
     const int zs = z0 - R, ze = z1 + R;            // step-1 planes [zs, ze)
+    // Edge pacing: the first and last tile columns read fewer bytes (their
+    // out-of-grid halo costs none) and would march ahead of their neighbours.
+    const int pace = (a.gx >= 3 && (tile_x == 0 || tile_x == a.gx - 1)) ? a.pace : 0;
     const int zlo = max(z0 - 2 * R, 0);
     const int zhi = min(z1 + 2 * R, a.nz);
     const int64_t plane = (int64_t)a.pitch * a.ny;
@@ -198,6 +205,17 @@ __device__ __forceinline__ void zmarch2_body(const SweepArgs &a, int b)
             const bool st2 = zq >= z0 && zq < z1;
             float *buf1 = lds1 + (j & 1) * LBUF;
             float *buf2 = lds2 + (j & 1) * L2BUF;
+            if (pace) {  // uniform for the workgroup; a pause of about 4 * pace * 64 cycles
+                switch (pace) {
+                case 1: __builtin_amdgcn_s_sleep(4); break;
+                case 2: __builtin_amdgcn_s_sleep(8); break;
+                case 3: __builtin_amdgcn_s_sleep(12); break;
+                case 4: __builtin_amdgcn_s_sleep(16); break;
+                case 5: __builtin_amdgcn_s_sleep(20); break;
+                case 6: __builtin_amdgcn_s_sleep(24); break;
+                default: __builtin_amdgcn_s_sleep(28); break;
+                }
+            }
 
             // u^{n-1} and kappa of plane z on E.
             V up, kp;

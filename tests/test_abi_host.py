@@ -191,6 +191,17 @@ def test_two_step_tile_and_validation():
         g = p.stencil_get_tile2(ctx)
         assert (g.bx, g.by, g.dz) == (tt.bx, tt.by, 8)
     assert p.stencil_get_tile(ctx).kind == p.TILE_ZMARCH  # the one-step tile is unchanged
+    # pf bits 1-3: edge pacing codes 0..7 on any compiled two-step shape;
+    # larger values are refused.
+    tt = tiles[0]
+    for pf in (tt.pf | (5 << 1), tt.pf | (7 << 1)):
+        tt.pf = pf
+        p.stencil_set_tile(ctx, tt)
+        assert p.stencil_get_tile2(ctx).pf == pf
+    tt.pf = 16
+    with pytest.raises(p.StencilError) as e:
+        p.stencil_set_tile(ctx, tt)
+    assert e.value.status == p.EUNSUPPORTED
     n = 64 * 48 * 40 * 4
     base = 1 << 40
     k, a, b, c, d = (base + i * 2 * n for i in range(5))

@@ -68,6 +68,9 @@ def test_two_step_bits_equal_one_step(R, shape):
         for dz in (1, 7, 16, nz):
             for xcd in (1, 0):
                 tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, t.ry, dz, t.vw, xcd, t.pf))
+            # Edge pacing (pf bits 1-3; active with three or more tile
+            # columns, e.g. 260 points wide): timing only, the same bits.
+            tiles.append(p.make_tile(p.TILE_ZMARCH2, t.bx, t.by, t.ry, dz, t.vw, 1, t.pf | (5 << 1)))
     assert tiles
     for t in tiles:
         got = _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal=2, tile2=t)
