@@ -178,8 +178,12 @@ def stencil_last_error(ctx) -> str:
     return _lib.stencil_last_error(ctx).decode()
 
 
-def make_tile(kind=TILE_ZMARCH, bx=0, by=0, ry=1, dz=0, vw=0, xcd=1, pf=0) -> StencilTile:
-    return StencilTile(kind, bx, by, ry, dz, vw, xcd, pf)
+def make_tile(kind=TILE_ZMARCH, bx=0, by=0, ry=1, dz=0, vw=0, xcd=1, pf=0, pace=0) -> StencilTile:
+    """A tile (stencil_tile). pf bit 0: prefetch; for two-step tiles, pace 0..7
+    is the edge pacing code (stored in pf bits 1-3)."""
+    if not 0 <= pace <= 7:
+        raise ValueError("pace must be in 0..7")
+    return StencilTile(kind, bx, by, ry, dz, vw, xcd, pf | (pace << 1))
 
 
 def stencil_init(nx, ny, nz, h, dt, vmax, radius=4, device=0, tile: StencilTile | None = None, storage=F32,
