@@ -9,6 +9,13 @@ spills SGPRs or VGPRs or uses per-lane scratch: spilled registers change a
 kernel's schedule and memory traffic in ways the tests do not see, so the
 product carries none. The per-kernel table is written to
 _build/resource_usage.txt.
+
+The build also disassembles the gfx950 code objects it produced and fails
+when a vector-memory store of more than 8 bytes is directly followed by a
+VALU instruction that writes one of the store's data registers: the store
+reads its data after it issues, so without one instruction in between the
+new value can be stored instead of the old one (a wait state the compiler
+is meant to insert). Findings go to _build/store_hazards.txt.
 """
 from __future__ import annotations
 
@@ -28,6 +35,8 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Rpass-analysis=kernel-resource-usage"]
 USAGE = os.path.join(OUT, "resource_usage.txt")
+HAZARDS = os.path.join(OUT, "store_hazards.txt")
+LLVM_BIN = os.environ.get("ROCM_LLVM_BIN", "/opt/rocm/llvm/bin")
 
 _REMARK = re.compile(r"remark:\s+(Function Name|TotalSGPRs|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|"
                      r"Occupancy \[waves/SIMD\]|SGPRs Spill|VGPRs Spill|LDS Size \[bytes/block\]):\s*(\S+)")
@@ -55,6 +64,65 @@ def spill_offenders(records: list) -> list:
     """Kernels that spill registers or use scratch memory."""
     return [r for r in records
             if r.get("sgprs_spill", 0) or r.get("vgprs_spill", 0) or r.get("scratchsize", 0)]
+
+
+# The data operand: first for buffer stores (vdata, vaddr, ...), second for
+# global / flat / scratch stores (vaddr, vdata, ...).
+_STORE = re.compile(r"^\s*(?:buffer_store_(?:dwordx[34]|b96|b128)\s+(v\d+|v\[\d+:\d+\])"
+                    r"|(?:global|flat|scratch)_store_(?:dwordx[34]|b96|b128)\s+\S+,\s*(v\d+|v\[\d+:\d+\]))")
+_VALU_DST = re.compile(r"^\s*v_\w+\s+(v\d+|v\[\d+:\d+\])")
+_FUNC = re.compile(r"^[0-9a-f]+ <([^>]+)>:")
+
+
+def _vgprs(tok: str) -> set:
+    m = re.match(r"v\[(\d+):(\d+)\]", tok)
+    if m:
+        return set(range(int(m.group(1)), int(m.group(2)) + 1))
+    return {int(tok[1:])}
+
+
+def store_data_hazards(disasm: str) -> list:
+    """(kernel, store, next instruction) for every store of more than 8 bytes
+    whose next instruction in address order is a VALU write of one of the
+    store's data VGPRs (llvm-objdump text of a gfx950 code object)."""
+    out, func, pending = [], None, None
+    for line in disasm.splitlines():
+        m = _FUNC.match(line)
+        if m:
+            func, pending = m.group(1), None
+            continue
+        text = line.split("//")[0].split(";")[0].strip()
+        if not text or text.endswith(":"):
+            continue
+        if pending is not None:
+            v = _VALU_DST.match(text)
+            if v and _vgprs(v.group(1)) & pending[1]:
+                out.append((func, pending[0], text))
+            pending = None
+        st = _STORE.match(text)
+        if st:
+            pending = (text, _vgprs(st.group(1) or st.group(2)))
+    return out
+
+
+def disassemble(obj: str) -> str:
+    """llvm-objdump text of the gfx950 code object embedded in one of this
+    build's object files (its .hip_fatbin bundle)."""
+    fat, co = obj + ".fatbin", obj + ".co"
+    heads = subprocess.run([os.path.join(LLVM_BIN, "llvm-objdump"), "-h", obj], check=True, capture_output=True,
+                           text=True).stdout
+    if ".hip_fatbin" not in heads:
+        return ""  # no device code in this object
+    subprocess.run([os.path.join(LLVM_BIN, "llvm-objcopy"), "--dump-section", f".hip_fatbin={fat}", obj,
+                    obj + ".strip"], check=True, capture_output=True)
+    os.remove(obj + ".strip")
+    subprocess.run([os.path.join(LLVM_BIN, "clang-offload-bundler"), "--unbundle", "--type=o", f"--input={fat}",
+                    f"--targets=hipv4-amdgcn-amd-amdhsa--{ARCH}", f"--output={co}"], check=True, capture_output=True)
+    r = subprocess.run([os.path.join(LLVM_BIN, "llvm-objdump"), "-d", f"--mcpu={ARCH}", co], check=True,
+                       capture_output=True, text=True)
+    os.remove(fat)
+    os.remove(co)
+    return r.stdout
 
 
 ARCH = "gfx950"
@@ -124,6 +192,16 @@ def build(verbose: bool = False) -> str:
                            "\n".join(f"  {r['name']}: SGPR spill {r.get('sgprs_spill')}, "
                                       f"VGPR spill {r.get('vgprs_spill')}, scratch {r.get('scratchsize')} B/lane"
                                       for r in bad))
+    hazards = []
+    for obj, _ in _jobs():
+        hazards += store_data_hazards(disassemble(obj))
+    with open(HAZARDS, "w") as f:
+        f.write(f"stores of more than 8 bytes directly followed by a VALU write of their data: {len(hazards)}\n")
+        for k, st, nx in hazards:
+            f.write(f"{k}\n    {st}\n    {nx}\n")
+    if hazards:
+        raise RuntimeError("store data overwritten by the next instruction (see " + HAZARDS + "):\n" +
+                           "\n".join(f"  {k}: {st} / {nx}" for k, st, nx in hazards[:10]))
     link = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + [o for o, _ in _jobs()]
     if verbose:
         print(" ".join(link), file=sys.stderr)

@@ -1,6 +1,7 @@
-"""The library build's register-spill check: hipcc's per-kernel resource
-remarks are parsed, every compiled kernel is listed, and a kernel that spills
-SGPRs or VGPRs or uses scratch fails the build."""
+"""The library build's checks: hipcc's per-kernel resource remarks are
+parsed, every compiled kernel is listed, and a kernel that spills SGPRs or
+VGPRs or uses scratch fails the build; the disassembled code objects are
+scanned for a store whose data registers the next instruction overwrites."""
 import importlib.util
 import os
 
@@ -72,3 +73,44 @@ def test_built_library_passed_the_check():
     for r in recs:
         assert int(r.get("sgprs_spill", 0)) == 0 and int(r.get("vgprs_spill", 0)) == 0, r["name"]
         assert int(r.get("scratchsize", 0)) == 0, r["name"]
+
+
+DISASM = """\
+0000000000001000 <_Z3fooPf>:
+	buffer_store_dwordx4 v[68:71], v100, s[36:39], s10 offen nt // 000000001000: E07E1000 0A094464
+	v_cndmask_b32_e64 v68, 0, 1, s[42:43]                      // 000000001008: D1000044 00A90280
+	buffer_store_dwordx4 v[20:23], v1, s[36:39], s10 offen nt  // 000000001010: E07E1000 0A091401
+	s_nop 0                                                    // 000000001018: BF800000
+	v_mov_b32_e32 v21, 0                                       // 00000000101C: 7E2A0280
+	buffer_store_dwordx2 v[30:31], v1, s[36:39], 0 offen       // 000000001020: E0741000 80091E01
+	v_mov_b32_e32 v30, 0                                       // 000000001028: 7E3C0280
+0000000000002000 <_Z3barPf>:
+	global_store_dwordx4 v[0:1], v[8:11], off                  // 000000002000: DC7C0000 007D0800
+	v_lshl_add_u64 v[0:1], v[0:1], 0, s[6:7]                   // 000000002008: D2080000 00190100
+	global_store_dwordx4 v[0:1], v[8:11], off                  // 000000002010: DC7C0000 007D0800
+	v_add_f32_e32 v9, v2, v3                                   // 000000002018: 02120702
+	buffer_store_dwordx4 v[40:43], v1, s[36:39], 0 offen       // 000000002020: E07C1000 80092801
+	v_add_f32_e32 v44, v2, v3                                  // 000000002028: 02580702
+"""
+
+
+def test_store_data_hazards_are_found():
+    # A store of more than 8 bytes whose next instruction is a VALU write of
+    # one of its data registers; not after a wait state, not for an 8-byte
+    # store, not for a write of a global store's address or of another
+    # register.
+    b = _build_module()
+    got = b.store_data_hazards(DISASM)
+    assert [(k, st.split()[0], nx.split()[0]) for k, st, nx in got] == [
+        ("_Z3fooPf", "buffer_store_dwordx4", "v_cndmask_b32_e64"),
+        ("_Z3barPf", "global_store_dwordx4", "v_add_f32_e32"),
+    ]
+
+
+def test_built_library_has_no_store_data_hazard():
+    b = _build_module()
+    if not os.path.exists(b.HAZARDS):
+        pytest.skip("library not built in this tree")
+    with open(b.HAZARDS) as f:
+        first = f.readline()
+    assert first.strip().endswith(": 0"), first
