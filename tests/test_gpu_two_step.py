@@ -55,8 +55,8 @@ def _run(v, dt, vmax, R, u0, um1, idx, amp, nt, temporal, tile2=None):
 
 
 @pytest.mark.parametrize("R,shape", [(4, (72, 45, 37)), (3, (72, 45, 37)), (5, (72, 45, 37)), (4, (61, 29, 23)),
-                                     (4, (260, 67, 19)), (5, (61, 29, 23)), (4, (12, 10, 6)), (4, (1, 1, 1)),
-                                     (4, (8, 40, 3))])
+                                     (4, (260, 67, 19)), (3, (260, 67, 19)), (5, (200, 45, 21)), (5, (61, 29, 23)),
+                                     (4, (12, 10, 6)), (4, (1, 1, 1)), (4, (8, 40, 3))])
 def test_two_step_bits_equal_one_step(R, shape):
     nt = 7  # three two-step launches and one closing one-step launch
     v, dt, vmax, u0, um1, idx, amp = _case(shape, 50 + R, R, nt)
