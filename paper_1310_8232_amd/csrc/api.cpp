@@ -573,8 +573,16 @@ std::vector<stencil_tile> make_candidates(stencil_ctx *ctx, const stencil_tune_o
     const stencil_desc &d = ctx->d;
     if (o.temporal == 2) {
         const int vw = vec4_ok(ctx) ? 4 : 1;
-        // Two-step shapes x march depths x XCD order.
-        const int64_t dzs[] = {16, 32, 64, 128, 256, d.nz};
+        // Two-step shapes x march depths x XCD order. A two-step workgroup
+        // covers a large tile, so a grid gives few of them: besides the
+        // powers of two, depths that split nz into k equal chunks (k = 2..8)
+        // let the search find a workgroup count that fills whole rounds of
+        // CUs.
+        std::vector<int64_t> dzs = {16, 32, 64, 128, 256, d.nz};
+        for (int64_t k = 2; k <= 8; ++k) {
+            const int64_t dz = (d.nz + k - 1) / k;
+            if (dz >= 16) dzs.push_back(dz);
+        }
         for (int i = 0; i < p1310::zmarch2_variant_count(); ++i) {
             const Z2Variant *v = p1310::zmarch2_variant(i);
             if (v->R != ctx->R || v->st != ctx->st || v->vw != vw) continue;
